@@ -1,0 +1,147 @@
+/*
+ * fblisa.h -- C ABI of the MI355X (gfx950) FB-LISA hot-path library, libfblisa.so.
+ *
+ * The library computes, on one GPU, the three operations FB-LISA (arXiv 2605.12085)
+ * spends its time in, for 3D circular cone-beam CT with data split into whole views:
+ *
+ *   fb_lisa_forward      A_N x over a mini-batch N of views, optionally fused with the
+ *                        residual A_N x - b_N and the mini-batch objective
+ *                        f_N(x) = n_theta/(2|N|) ||A_N x - b_N||^2      (eq. 2.5, Alg. 1 Step 2b)
+ *   fb_lisa_backproject  the matched adjoint: grad f_N = n_theta/|N| A_N^T r  (eq. 2.5, Step 2b)
+ *   fb_lisa_step         the prox-gradient trial xbar = prox_{alpha R}(x - alpha g) with
+ *                        R = mu ||.||_1 + indicator[lo, hi], and the two inner products
+ *                        of the sufficient-decrease test (2.3)           (Alg. 1 Step 2c)
+ *
+ * The discretised operator A (the paper uses an unspecified third-party projector)
+ * is Joseph's ray-driven method with bilinear interpolation:
+ *   - voxel (i,j,k) centre ((i-(nx-1)/2)hx, (j-(ny-1)/2)hy, (k-(nz-1)/2)hz) mm,
+ *     volumes are C arrays [nz][ny][nx] (x fastest);
+ *   - view v at angle theta_v: source SOD(cos, sin, 0), detector centre
+ *     (SOD-SDD)(cos, sin, 0), detector axes e_u = (-sin, cos, 0), e_v = (0, 0, 1);
+ *   - pixel (iu, iv) centre at detector centre + (iu-(nu-1)/2)du e_u + (iv-(nv-1)/2)dv e_v,
+ *     projections are C arrays [view][nv][nu] (u fastest); one ray per pixel;
+ *   - a ray marches the slices of its dominant index axis (largest |q-s|/h, ties to the
+ *     lower axis x < y < z), samples each slice bilinearly (taps outside the volume are
+ *     zero) and is scaled by the slice-to-slice path length h_a |q-s| / |q_a - s_a|.
+ * Rays whose dominant axis would be z (cone angles beyond 45 degrees) are not supported:
+ * plan creation rejects such geometries.
+ *
+ * Conventions for every call:
+ *   - Device pointers are plain HIP device addresses owned by the caller; array buffers
+ *     are contiguous in the layouts above and 16-byte aligned, scalar outputs (loss_dev,
+ *     red_dev) 8-byte aligned.  Host pointers (geometry,
+ *     angles, view lists) are read during the call only.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Compute calls only enqueue
+ *     work: they never synchronise the device.  A plan serves one stream at a time.
+ *   - Every function returns FBL_OK (0) or an FBL_E_* code and then sets a thread-local
+ *     message readable with fbl_last_error().  Argument checks happen on the host before
+ *     anything is enqueued: a call that fails a check launches nothing.  Faults inside
+ *     kernels surface at the caller's next synchronisation.
+ */
+#ifndef FBLISA_H
+#define FBLISA_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define FBL_API __attribute__((visibility("default")))
+#else
+#define FBL_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+    FBL_OK = 0,
+    FBL_E_INVALID = 1,   /* null pointer, bad size, misaligned buffer, bad scalar */
+    FBL_E_GEOMETRY = 2,  /* geometry fails a precondition (see fbl_geometry_check) */
+    FBL_E_RANGE = 3,     /* view id or batch size out of range */
+    FBL_E_DTYPE = 4,     /* unsupported storage type */
+    FBL_E_HIP = 5,       /* a HIP runtime call failed; the message holds its error string */
+    FBL_E_NOMEM = 6      /* device or host allocation failed */
+};
+
+/* Storage types of the volume (x, xbar) and of the measured data b. */
+enum {
+    FBL_F32 = 0,
+    FBL_BF16 = 1,
+    FBL_F16 = 2
+};
+
+/* Scan geometry (millimetres, radians).  `angles` is a host array of n_views angles, or
+ * NULL for the uniform set 2*pi*v/n_views (the paper's acquisitions are uniform over
+ * [0, 2*pi)). */
+typedef struct {
+    int64_t nx, ny, nz;
+    double hx, hy, hz;
+    int64_t nu, nv;
+    double du, dv;
+    double sod, sdd;
+    int64_t n_views;
+    const double *angles;
+} fbl_geometry;
+
+typedef struct fbl_plan fbl_plan;
+
+/* Host-only geometry validation; touches no device.  Checks: every count >= 1 (each at
+ * most 2^24) and nx*ny*nz < 2^31, nu*nv < 2^31; positive finite spacings; SOD > 0;
+ * SDD > SOD; SOD and SDD - SOD both exceed the half-diagonal of the volume grown by two
+ * voxels on every side (the volume lies strictly between source and detector); finite
+ * angles; no ray with z as its dominant axis.  Returns FBL_OK or FBL_E_GEOMETRY
+ * (FBL_E_INVALID for NULL). */
+FBL_API int fbl_geometry_check(const fbl_geometry *g);
+
+/* Create a plan on the current HIP device: validates the geometry, computes the per-view,
+ * per-column ray parameters in FP64 on the host, and allocates the plan's device tables,
+ * its reduction workspace and a [max_batch][nv][nu] FP32 scratch used by the
+ * backprojection.  max_batch in [1, n_views].  vol_dtype is FBL_F32, FBL_BF16 or
+ * FBL_F16 (x and xbar); proj_dtype is FBL_F32 or FBL_F16 (b).  On failure *out is NULL.
+ * The plan is released with fbl_plan_destroy (NULL is accepted). */
+FBL_API int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype, int32_t max_batch,
+                    fbl_plan **out);
+FBL_API void fbl_plan_destroy(fbl_plan *plan);
+
+/* Forward projection of a mini-batch of views (eq. 2.5; Alg. 1 Steps 2b and 2c).
+ *   x         device, [nz][ny][nx] in the plan's vol_dtype
+ *   views     host, B view ids in [0, n_views) (duplicates allowed); B in [1, max_batch]
+ *   b         device, full data [n_views][nv][nu] in proj_dtype, or NULL
+ *   y         device FP32 [B][nv][nu]: y = A_views x, or the residual A_views x - b[views]
+ *             when b is given (row k of y belongs to views[k])
+ *   loss_dev  device, one double, or NULL: *loss_dev = loss_scale * sum(y^2), summed in
+ *             FP64 in a fixed order (deterministic); pass loss_scale = n_theta/(2B) for
+ *             f_N of (2.5).  Overwritten, not accumulated. */
+FBL_API int fb_lisa_forward(fbl_plan *plan, const void *x, const int32_t *views, int32_t B, const void *b, float *y,
+                    double *loss_dev, double loss_scale, void *stream);
+
+/* Matched backprojection (eq. 2.5: grad f_N = n_theta/|N| A_N^T (A_N x - b_N)).
+ *   r           device FP32 [B][nv][nu] (row k belongs to views[k])
+ *   views, B    as for fb_lisa_forward
+ *   grad_scale  scalar applied to the result (n_theta/B for the gradient of (2.5))
+ *   g           device FP32 [nz][ny][nx], overwritten with grad_scale * A_views^T r.
+ * Voxel-driven and free of atomics: the result does not depend on launch order. */
+FBL_API int fb_lisa_backproject(fbl_plan *plan, const float *r, const int32_t *views, int32_t B, double grad_scale,
+                        float *g, void *stream);
+
+/* Prox-gradient trial of Alg. 1 Step 2c and the inner products of (2.3).
+ *   x, g      device, [nz][ny][nx]; x in vol_dtype, g FP32
+ *   alpha > 0, mu >= 0, 0 <= lo <= hi (hi may be +infinity)
+ *   xbar      device, vol_dtype: xbar = min(max(x - alpha g - alpha mu, lo), hi), formed
+ *             in FP64 and rounded once to the storage type (may not alias x or g)
+ *   red_dev   device, three doubles: red[0] = <g, xbar - x>, red[1] = ||xbar - x||^2 with
+ *             xbar the stored (rounded) value, red[2] = ||g||^2; FP64 sums in a fixed
+ *             order (deterministic). */
+FBL_API int fb_lisa_step(fbl_plan *plan, const void *x, const float *g, double alpha, double mu, double lo, double hi,
+                 void *xbar, double *red_dev, void *stream);
+
+/* Message of the last failed call on this thread ("" if none); valid until the next
+ * call on the same thread. */
+FBL_API const char *fbl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FBLISA_H */

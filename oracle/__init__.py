@@ -254,6 +254,22 @@ def prox(v, alpha: float, mu: float, lo: float = 0.0, hi: float = math.inf) -> n
     return np.minimum(np.maximum(_f64(v) - alpha * mu, lo), hi)
 
 
+def prox_step(x, grad, alpha: float, mu: float, lo: float = 0.0, hi: float = math.inf, storage=None):
+    """Trial point of Algorithm 1 Step 2c and the inner products of (2.3).
+
+    xbar = prox(x - alpha grad); with ``storage`` (a numpy dtype such as float32) the
+    trial point is rounded to that storage type, as a stored iterate would be, before
+    d = xbar - x is formed.  Returns (xbar, <grad, d>, ||d||^2, ||grad||^2).
+    """
+    x64, g64 = _f64(x), _f64(grad)
+    xbar = prox(x64 - alpha * g64, alpha, mu, lo, hi)
+    if storage is not None:
+        xbar = xbar.astype(storage).astype(np.float64)
+    d = xbar - x64
+    return xbar, float(np.dot(g64.ravel(), d.ravel())), float(np.dot(d.ravel(), d.ravel())), \
+        float(np.dot(g64.ravel(), g64.ravel()))
+
+
 # ----------------------------------------------------------------------------------
 # line search and Algorithm 1
 # ----------------------------------------------------------------------------------

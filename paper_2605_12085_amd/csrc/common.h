@@ -1,0 +1,102 @@
+// Shared declarations of the gfx950 FB-LISA library: device-side parameter tables,
+// the plan, and the launch functions each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "../../include/fblisa.h"
+
+namespace fbl {
+
+// Views per kernel launch: the list travels by value in the kernel arguments, so a
+// call needs no host-to-device copy.  Larger batches are split into several launches.
+constexpr int kViewsPerLaunch = 256;
+
+struct ViewList {
+    int32_t v[kViewsPerLaunch];
+};
+
+// Per-(view, detector column) ray parameters, computed on the host in FP64.
+// All rays of a column share their dominant axis a (x or y), their in-slice horizontal
+// index coordinate xi(m) = xi0 + m*xi1 and their ray parameter tau(m) = t0 + m*t1 at
+// slice m; the vertical index coordinate of row iv is eta = cz + tau*V[iv].  The ray
+// length per slice is w = wa * sqrt(l2 + v2[iv]).
+//
+// Index coordinates reach a few thousand, where an FP32 value resolves only ~1e-4 of a
+// voxel; the kernels therefore form positions in FP64 once per chunk of slices, split
+// them into an integer voxel index and an FP32 offset, and step the offset in FP32
+// inside the chunk (offsets stay below the chunk length, resolved to ~1e-6 voxel).
+struct ColParam {
+    double xi0, xi1;  // horizontal index coordinate on slice m (xi0 + m*xi1)
+    double t0, t1;    // ray parameter on slice m (t0 + m*t1), 0 at source, 1 at pixel
+    float wa;         // h_a / |q_a - s_a|
+    float l2;         // (q_x - s_x)^2 + (q_y - s_y)^2, mm^2
+    int32_t axis;     // 0: slices are x = const (xi is y), 1: slices are y = const (xi is x)
+    int32_t pad;
+};
+
+// Per-view quantities used by the voxel-driven backprojection to find the detector
+// columns near a voxel: the projection u(p) = sdd (p.e_u)/(sod - p.n) of a point p.
+struct ViewParam {
+    float c, s;       // cos, sin of the view angle
+    float pad0, pad1;
+};
+
+struct Geo {
+    int nx, ny, nz;
+    int nu, nv;
+    float hx, hy, hz;
+    float du, dv;
+    float sod, sdd;
+    double cz;       // (nz-1)/2: the vertical index coordinate of the source plane
+    float cu, cv;    // (nu-1)/2, (nv-1)/2
+    float dvz;       // dv / hz
+    int64_t np;      // nu*nv
+};
+
+struct DeviceTables {
+    const ColParam *col;    // [n_views][nu]
+    const double *rowV;     // [nv] vertical index slope (iv-(nv-1)/2)*dv/hz
+    const float *rowV2;     // [nv] (iv-(nv-1)/2)^2 dv^2, mm^2
+    const ViewParam *view;  // [n_views]
+};
+
+}  // namespace fbl
+
+struct fbl_plan {
+    fbl_geometry geom;            // host copy; geom.angles points into angles_host
+    double *angles_host;
+    int device;
+    int32_t vol_dtype, proj_dtype, max_batch;
+    fbl::Geo geo;
+    fbl::ColParam *d_col;
+    double *d_rowV;
+    float *d_rowV2;
+    fbl::ViewParam *d_view;
+    double *d_partials;           // FP64 per-block partial sums
+    int64_t n_partials;
+    float *d_rw;                  // [max_batch][nv][nu] weighted residual for the backprojection
+    int fp_blocks_per_view;       // forward launch shape
+};
+
+namespace fbl {
+
+// Launch functions (stream-ordered, no synchronisation).  Each returns hipSuccess or the
+// launch error.
+hipError_t launch_forward(const fbl_plan *p, const void *x, const ViewList &vl, int nb, int first,
+                          const void *b, float *y, bool want_loss, hipStream_t st);
+hipError_t launch_finalize_sum(double *partials, int64_t n, int ncomp, double scale, double *out,
+                               hipStream_t st);
+hipError_t launch_prescale(const fbl_plan *p, const float *r, const ViewList &vl, int nb, int first,
+                           double grad_scale, float *rw, hipStream_t st);
+hipError_t launch_backproject(const fbl_plan *p, const float *rw, const ViewList &vl, int nb, int first,
+                              bool accumulate, float *g, hipStream_t st);
+hipError_t launch_step(const fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo,
+                       double hi, void *xbar, int64_t *n_partials_used, hipStream_t st);
+
+int step_blocks(const fbl_plan *p);
+
+}  // namespace fbl

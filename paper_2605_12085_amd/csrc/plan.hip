@@ -1,0 +1,375 @@
+// Host side of libfblisa: geometry validation, FP64 ray set-up into the plan's device
+// tables, argument checks, and the C ABI declared in include/fblisa.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace fbl {
+int forward_blocks_per_view(const Geo &g);
+}
+
+using namespace fbl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok()
+{
+    g_err.clear();
+    return FBL_OK;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(FBL_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+double view_angle(const fbl_geometry &g, int64_t v)
+{
+    if (g.angles) return g.angles[v];
+    return 2.0 * M_PI * (double)v / (double)g.n_views;
+}
+
+// FP64 ray geometry of one detector column, evaluated without fused multiply-adds in
+// the order of the conventions (source, pixel centre, index coordinates P and D), so the
+// dominant-axis decision is reproducible bit for bit.
+#pragma clang fp contract(off)
+struct ColumnGeom {
+    double s[2], q[2];
+    double P[2], D[2];
+};
+
+ColumnGeom column_geom(const fbl_geometry &g, int64_t v, int64_t iu)
+{
+    ColumnGeom cg;
+    const double th = view_angle(g, v);
+    const double c = std::cos(th), sn = std::sin(th);
+    const double dc = g.sod - g.sdd;
+    const double u = ((double)iu - 0.5 * (double)(g.nu - 1)) * g.du;
+    cg.s[0] = g.sod * c;
+    cg.s[1] = g.sod * sn;
+    cg.q[0] = dc * c + u * (-sn);
+    cg.q[1] = dc * sn + u * c;
+    const double h[2] = {g.hx, g.hy};
+    const int64_t n[2] = {g.nx, g.ny};
+    for (int k = 0; k < 2; ++k) {
+        cg.P[k] = cg.s[k] / h[k] + 0.5 * (double)(n[k] - 1);
+        cg.D[k] = (cg.q[k] - cg.s[k]) / h[k];
+    }
+    return cg;
+}
+
+// Largest |D_z| over the detector rows: |(v - 0) / hz| with v the row centre height.
+double max_abs_dz(const fbl_geometry &g)
+{
+    double m = 0.0;
+    for (int64_t iv = 0; iv < g.nv; ++iv) {
+        const double v = ((double)iv - 0.5 * (double)(g.nv - 1)) * g.dv;
+        const double dz = std::fabs((v - 0.0) / g.hz);
+        if (dz > m) m = dz;
+    }
+    return m;
+}
+#pragma clang fp contract(on)
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int check_geometry(const fbl_geometry *g)
+{
+    if (!g) return fail(FBL_E_INVALID, "geometry is NULL");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1 || g->nu < 1 || g->nv < 1 || g->n_views < 1)
+        return fail(FBL_E_GEOMETRY, "every count must be >= 1 (nx=%lld ny=%lld nz=%lld nu=%lld nv=%lld n_views=%lld)",
+                    (long long)g->nx, (long long)g->ny, (long long)g->nz, (long long)g->nu, (long long)g->nv,
+                    (long long)g->n_views);
+    if (g->nx > (1 << 24) || g->ny > (1 << 24) || g->nz > (1 << 24) || g->nu > (1 << 24) || g->nv > (1 << 24))
+        return fail(FBL_E_GEOMETRY, "a dimension exceeds 2^24");
+    if ((double)g->nx * (double)g->ny * (double)g->nz >= 2147483648.0)
+        return fail(FBL_E_GEOMETRY, "nx*ny*nz must be below 2^31");
+    if ((double)g->nu * (double)g->nv >= 2147483648.0) return fail(FBL_E_GEOMETRY, "nu*nv must be below 2^31");
+    if (g->n_views > (1 << 24)) return fail(FBL_E_GEOMETRY, "n_views exceeds 2^24");
+    if (!finite_pos(g->hx) || !finite_pos(g->hy) || !finite_pos(g->hz) || !finite_pos(g->du) || !finite_pos(g->dv))
+        return fail(FBL_E_GEOMETRY, "voxel and pixel sizes must be finite and positive");
+    if (!finite_pos(g->sod) || !std::isfinite(g->sdd)) return fail(FBL_E_GEOMETRY, "SOD must be finite and positive");
+    if (!(g->sdd > g->sod)) return fail(FBL_E_GEOMETRY, "SDD (%g) must exceed SOD (%g)", g->sdd, g->sod);
+    // half-diagonal of the volume grown by two voxels on every side (the backprojection
+    // projects points up to that far out)
+    const double ex = 0.5 * (double)(g->nx + 4) * g->hx, ey = 0.5 * (double)(g->ny + 4) * g->hy,
+                 ez = 0.5 * (double)(g->nz + 4) * g->hz;
+    const double half = std::sqrt(ex * ex + ey * ey + ez * ez);
+    if (!(g->sod > half) || !(g->sdd - g->sod > half))
+        return fail(FBL_E_GEOMETRY,
+                    "the volume must lie strictly between source and detector: SOD=%g and SDD-SOD=%g must exceed "
+                    "the padded half-diagonal %g",
+                    g->sod, g->sdd - g->sod, half);
+    if (g->angles)
+        for (int64_t v = 0; v < g->n_views; ++v)
+            if (!std::isfinite(g->angles[v])) return fail(FBL_E_GEOMETRY, "angle %lld is not finite", (long long)v);
+    const double dz = max_abs_dz(*g);
+    for (int64_t v = 0; v < g->n_views; ++v)
+        for (int64_t iu = 0; iu < g->nu; ++iu) {
+            const ColumnGeom cg = column_geom(*g, v, iu);
+            const double mxy = std::fmax(std::fabs(cg.D[0]), std::fabs(cg.D[1]));
+            if (!(mxy >= dz))
+                return fail(FBL_E_GEOMETRY,
+                            "view %lld column %lld has rays whose dominant axis is z (cone angle too large)",
+                            (long long)v, (long long)iu);
+        }
+    return FBL_OK;
+}
+
+template <typename T>
+int dev_upload(T **dst, const std::vector<T> &src)
+{
+    *dst = nullptr;
+    hipError_t e = hipMalloc((void **)dst, src.size() * sizeof(T));
+    if (e != hipSuccess) return fail(FBL_E_NOMEM, "hipMalloc of %zu bytes: %s", src.size() * sizeof(T), hipGetErrorString(e));
+    e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy of plan table");
+    return FBL_OK;
+}
+
+void free_plan(fbl_plan *p)
+{
+    if (!p) return;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (p->device >= 0 && cur != p->device) (void)hipSetDevice(p->device);
+    (void)hipFree(p->d_col);
+    (void)hipFree(p->d_rowV);
+    (void)hipFree(p->d_rowV2);
+    (void)hipFree(p->d_view);
+    (void)hipFree(p->d_partials);
+    (void)hipFree(p->d_rw);
+    if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);
+    delete[] p->angles_host;
+    delete p;
+}
+
+int check_call(const fbl_plan *p, const int32_t *views, int32_t B)
+{
+    if (!p) return fail(FBL_E_INVALID, "plan is NULL");
+    if (!views) return fail(FBL_E_INVALID, "views is NULL");
+    if (B < 1 || B > p->max_batch)
+        return fail(FBL_E_RANGE, "batch size %d outside [1, %d]", (int)B, (int)p->max_batch);
+    for (int32_t k = 0; k < B; ++k)
+        if (views[k] < 0 || views[k] >= p->geom.n_views)
+            return fail(FBL_E_RANGE, "views[%d] = %d outside [0, %lld)", (int)k, (int)views[k],
+                        (long long)p->geom.n_views);
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != p->device)
+        return fail(FBL_E_INVALID, "the current device (%d) is not the plan's device (%d)", cur, p->device);
+    return FBL_OK;
+}
+
+ViewList chunk(const int32_t *views, int first, int nb)
+{
+    ViewList vl;
+    std::memset(&vl, 0, sizeof vl);
+    for (int k = 0; k < nb; ++k) vl.v[k] = views[first + k];
+    return vl;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fbl_last_error(void) { return g_err.c_str(); }
+
+int fbl_geometry_check(const fbl_geometry *g)
+{
+    int rc = check_geometry(g);
+    return rc == FBL_OK ? ok() : rc;
+}
+
+int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype, int32_t max_batch, fbl_plan **out)
+{
+    if (!out) return fail(FBL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int rc = check_geometry(g);
+    if (rc != FBL_OK) return rc;
+    if (vol_dtype != FBL_F32 && vol_dtype != FBL_BF16 && vol_dtype != FBL_F16)
+        return fail(FBL_E_DTYPE, "vol_dtype %d is not FBL_F32, FBL_BF16 or FBL_F16", (int)vol_dtype);
+    if (proj_dtype != FBL_F32 && proj_dtype != FBL_F16)
+        return fail(FBL_E_DTYPE, "proj_dtype %d is not FBL_F32 or FBL_F16", (int)proj_dtype);
+    if (max_batch < 1 || max_batch > g->n_views)
+        return fail(FBL_E_RANGE, "max_batch %d outside [1, n_views=%lld]", (int)max_batch, (long long)g->n_views);
+
+    fbl_plan *p = new fbl_plan();
+    std::memset((void *)p, 0, sizeof *p);
+    p->device = -1;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return hip_fail(e, "hipGetDevice");
+    }
+    p->geom = *g;
+    p->angles_host = new double[g->n_views];
+    for (int64_t v = 0; v < g->n_views; ++v) p->angles_host[v] = view_angle(*g, v);
+    p->geom.angles = p->angles_host;
+    p->vol_dtype = vol_dtype;
+    p->proj_dtype = proj_dtype;
+    p->max_batch = max_batch;
+
+    Geo &G = p->geo;
+    G.nx = (int)g->nx; G.ny = (int)g->ny; G.nz = (int)g->nz;
+    G.nu = (int)g->nu; G.nv = (int)g->nv;
+    G.hx = (float)g->hx; G.hy = (float)g->hy; G.hz = (float)g->hz;
+    G.du = (float)g->du; G.dv = (float)g->dv;
+    G.sod = (float)g->sod; G.sdd = (float)g->sdd;
+    G.cz = 0.5 * (double)(g->nz - 1);
+    G.cu = (float)(0.5 * (double)(g->nu - 1));
+    G.cv = (float)(0.5 * (double)(g->nv - 1));
+    G.dvz = (float)(g->dv / g->hz);
+    G.np = g->nu * g->nv;
+
+    std::vector<ColParam> col((size_t)g->n_views * (size_t)g->nu);
+    for (int64_t v = 0; v < g->n_views; ++v)
+        for (int64_t iu = 0; iu < g->nu; ++iu) {
+            const ColumnGeom cg = column_geom(p->geom, v, iu);
+            ColParam &cp = col[(size_t)v * (size_t)g->nu + (size_t)iu];
+            const int a = std::fabs(cg.D[0]) >= std::fabs(cg.D[1]) ? 0 : 1;
+            const int b = 1 - a;
+            const double ha = a == 0 ? g->hx : g->hy;
+            // slice m is crossed at t = (m - P_a)/D_a; there xi = P_b + t D_b
+            const double t1 = 1.0 / cg.D[a], t0 = -cg.P[a] / cg.D[a];
+            const double r = cg.D[b] / cg.D[a];
+            cp.t1 = t1;
+            cp.t0 = t0;
+            cp.xi1 = r;
+            cp.xi0 = cg.P[b] - cg.P[a] * r;
+            const double ex = cg.q[0] - cg.s[0], ey = cg.q[1] - cg.s[1];
+            cp.wa = (float)(ha / std::fabs(cg.q[a] - cg.s[a]));
+            cp.l2 = (float)(ex * ex + ey * ey);
+            cp.axis = a;
+            cp.pad = 0;
+        }
+    std::vector<double> rowV((size_t)g->nv);
+    std::vector<float> rowV2((size_t)g->nv);
+    for (int64_t iv = 0; iv < g->nv; ++iv) {
+        const double v = ((double)iv - 0.5 * (double)(g->nv - 1)) * g->dv;
+        rowV[(size_t)iv] = v / g->hz;
+        rowV2[(size_t)iv] = (float)(v * v);
+    }
+    std::vector<ViewParam> vp((size_t)g->n_views);
+    for (int64_t v = 0; v < g->n_views; ++v) {
+        const double th = p->angles_host[v];
+        vp[(size_t)v].c = (float)std::cos(th);
+        vp[(size_t)v].s = (float)std::sin(th);
+    }
+    p->fp_blocks_per_view = forward_blocks_per_view(G);
+    const int64_t np_fp = (int64_t)max_batch * p->fp_blocks_per_view;
+    const int64_t np_step = 3 * (int64_t)step_blocks(p);
+    p->n_partials = np_fp > np_step ? np_fp : np_step;
+
+    if ((rc = dev_upload(&p->d_col, col)) != FBL_OK || (rc = dev_upload(&p->d_rowV, rowV)) != FBL_OK ||
+        (rc = dev_upload(&p->d_rowV2, rowV2)) != FBL_OK || (rc = dev_upload(&p->d_view, vp)) != FBL_OK) {
+        std::string msg = g_err;
+        free_plan(p);
+        g_err = msg;
+        return rc;
+    }
+    e = hipMalloc((void **)&p->d_partials, (size_t)p->n_partials * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_rw, (size_t)max_batch * (size_t)G.np * sizeof(float));
+    if (e != hipSuccess) {
+        free_plan(p);
+        return fail(FBL_E_NOMEM, "hipMalloc of plan workspace: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return ok();
+}
+
+void fbl_plan_destroy(fbl_plan *plan) { free_plan(plan); }
+
+int fb_lisa_forward(fbl_plan *p, const void *x, const int32_t *views, int32_t B, const void *b, float *y,
+                    double *loss_dev, double loss_scale, void *stream)
+{
+    int rc = check_call(p, views, B);
+    if (rc != FBL_OK) return rc;
+    if (!x || !y) return fail(FBL_E_INVALID, "x and y must be non-NULL");
+    if (!aligned16(x) || !aligned16(y) || (b && !aligned16(b)) || (loss_dev && !aligned8(loss_dev)))
+        return fail(FBL_E_INVALID, "arrays must be 16-byte aligned and loss_dev 8-byte aligned");
+    if (loss_dev && !std::isfinite(loss_scale)) return fail(FBL_E_INVALID, "loss_scale must be finite");
+    hipStream_t st = (hipStream_t)stream;
+    for (int first = 0; first < B; first += kViewsPerLaunch) {
+        const int nb = B - first < kViewsPerLaunch ? B - first : kViewsPerLaunch;
+        hipError_t e = launch_forward(p, x, chunk(views, first, nb), nb, first, b, y, loss_dev != nullptr, st);
+        if (e != hipSuccess) return hip_fail(e, "forward projection launch");
+    }
+    if (loss_dev) {
+        hipError_t e = launch_finalize_sum(p->d_partials, (int64_t)B * p->fp_blocks_per_view, 1, loss_scale, loss_dev, st);
+        if (e != hipSuccess) return hip_fail(e, "loss reduction launch");
+    }
+    return ok();
+}
+
+int fb_lisa_backproject(fbl_plan *p, const float *r, const int32_t *views, int32_t B, double grad_scale, float *g,
+                        void *stream)
+{
+    int rc = check_call(p, views, B);
+    if (rc != FBL_OK) return rc;
+    if (!r || !g) return fail(FBL_E_INVALID, "r and g must be non-NULL");
+    if (!aligned16(r) || !aligned16(g)) return fail(FBL_E_INVALID, "device buffers must be 16-byte aligned");
+    if (!std::isfinite(grad_scale)) return fail(FBL_E_INVALID, "grad_scale must be finite");
+    hipStream_t st = (hipStream_t)stream;
+    for (int first = 0; first < B; first += kViewsPerLaunch) {
+        const int nb = B - first < kViewsPerLaunch ? B - first : kViewsPerLaunch;
+        hipError_t e = launch_prescale(p, r, chunk(views, first, nb), nb, first, grad_scale, p->d_rw, st);
+        if (e != hipSuccess) return hip_fail(e, "residual weighting launch");
+    }
+    for (int first = 0; first < B; first += kViewsPerLaunch) {
+        const int nb = B - first < kViewsPerLaunch ? B - first : kViewsPerLaunch;
+        hipError_t e = launch_backproject(p, p->d_rw, chunk(views, first, nb), nb, first, first > 0, g, st);
+        if (e != hipSuccess) return hip_fail(e, "backprojection launch");
+    }
+    return ok();
+}
+
+int fb_lisa_step(fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo, double hi, void *xbar,
+                 double *red_dev, void *stream)
+{
+    if (!p) return fail(FBL_E_INVALID, "plan is NULL");
+    if (!x || !g || !xbar || !red_dev) return fail(FBL_E_INVALID, "x, g, xbar and red_dev must be non-NULL");
+    if (!aligned16(x) || !aligned16(g) || !aligned16(xbar) || !aligned8(red_dev))
+        return fail(FBL_E_INVALID, "arrays must be 16-byte aligned and red_dev 8-byte aligned");
+    if (xbar == x || (const void *)xbar == (const void *)g) return fail(FBL_E_INVALID, "xbar may not alias x or g");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(FBL_E_INVALID, "alpha must be finite and > 0");
+    if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(FBL_E_INVALID, "mu must be finite and >= 0");
+    if (!(lo >= 0.0) || !std::isfinite(lo) || !(hi >= lo))
+        return fail(FBL_E_INVALID, "bounds must satisfy 0 <= lo <= hi (lo finite)");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != p->device) return fail(FBL_E_INVALID, "the current device is not the plan's device");
+    hipStream_t st = (hipStream_t)stream;
+    int64_t nparts = 0;
+    e = launch_step(p, x, g, alpha, mu, lo, hi, xbar, &nparts, st);
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    e = launch_finalize_sum(p->d_partials, nparts, 3, 1.0, red_dev, st);
+    if (e != hipSuccess) return hip_fail(e, "step reduction launch");
+    return ok();
+}
+
+}  // extern "C"

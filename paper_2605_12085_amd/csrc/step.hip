@@ -1,0 +1,75 @@
+// Prox-gradient trial and the FP64 inner products of the sufficient-decrease test.
+#include "common.h"
+#include "device_util.h"
+
+namespace fbl {
+
+namespace {
+
+constexpr int kStepBlocks = 2048;   // 8 blocks per compute unit, grid-stride over the volume
+
+template <typename TV>
+__global__ __launch_bounds__(256) void step_kernel(const TV *__restrict__ x, const float *__restrict__ g,
+                                                   double alpha, double amu, double lo, double hi,
+                                                   TV *__restrict__ xbar, int64_t d, double *__restrict__ partials)
+{
+    // the trial point is formed exactly as written, (x - alpha g) - alpha mu, without
+    // fused multiply-adds, so it rounds like an FP64 evaluation of the prox on the host
+#pragma clang fp contract(off)
+    __shared__ double red[4];
+    double s_inner = 0.0, s_sq = 0.0, s_gg = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d; i += (int64_t)gridDim.x * 256) {
+        const double xv = (double)to_f32(x[i]);
+        const double gv = (double)g[i];
+        double v = (xv - alpha * gv) - amu;
+        v = fmin(fmax(v, lo), hi);
+        const TV out = from_f64<TV>(v);
+        xbar[i] = out;
+        const double dl = (double)to_f32(out) - xv;
+        s_inner += gv * dl;
+        s_sq += dl * dl;
+        s_gg += gv * gv;
+    }
+    const double a = block_sum_256(s_inner, red);
+    const double b = block_sum_256(s_sq, red);
+    const double c = block_sum_256(s_gg, red);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x] = a;
+        partials[3 * blockIdx.x + 1] = b;
+        partials[3 * blockIdx.x + 2] = c;
+    }
+}
+
+}  // namespace
+
+int step_blocks(const fbl_plan *p)
+{
+    const int64_t d = (int64_t)p->geo.nx * p->geo.ny * p->geo.nz;
+    const int64_t need = (d + 255) / 256;
+    return (int)(need < kStepBlocks ? need : kStepBlocks);
+}
+
+template <typename TV>
+static hipError_t launch_step_t(const fbl_plan *p, const void *x, const float *g, double alpha, double amu,
+                                double lo, double hi, void *xbar, int blocks, hipStream_t st)
+{
+    const int64_t d = (int64_t)p->geo.nx * p->geo.ny * p->geo.nz;
+    hipLaunchKernelGGL((step_kernel<TV>), dim3(blocks), dim3(256), 0, st, (const TV *)x, g, alpha, amu, lo, hi,
+                       (TV *)xbar, d, p->d_partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo,
+                       double hi, void *xbar, int64_t *n_partials_used, hipStream_t st)
+{
+    const int blocks = step_blocks(p);
+    *n_partials_used = blocks;
+    const double amu = alpha * mu;
+    switch (p->vol_dtype) {
+    case FBL_F32: return launch_step_t<float>(p, x, g, alpha, amu, lo, hi, xbar, blocks, st);
+    case FBL_BF16: return launch_step_t<__hip_bfloat16>(p, x, g, alpha, amu, lo, hi, xbar, blocks, st);
+    default: return launch_step_t<__half>(p, x, g, alpha, amu, lo, hi, xbar, blocks, st);
+    }
+}
+
+}  // namespace fbl

@@ -1,0 +1,270 @@
+"""GPU (HIP) path against the FP64 oracle, element by element, through the C ABI.
+
+Tolerance (float path, FP32 arithmetic against FP64): per view, relative l2 error
+<= 1e-5 and max abs error <= 1e-5 * max|oracle|; the prox trial is within one FP32 ulp
+of the oracle's stored trial point and its FP64 reductions agree to 1e-12 relative
+(1e-9 where single-ulp differences of the trial point enter); the loss to 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def fbl():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2605_12085_amd as fbl
+    return fbl
+
+
+def _t(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _cmp_views(gpu, ref, tol=TOL, what=""):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    for b in range(ref.shape[0]):
+        nr = np.linalg.norm(ref[b])
+        if nr == 0:
+            assert np.abs(gpu[b]).max() == 0, what
+            continue
+        rel = np.linalg.norm(gpu[b] - ref[b]) / nr
+        mx = np.abs(gpu[b] - ref[b]).max() / np.abs(ref[b]).max()
+        assert rel <= tol and mx <= tol, "%s view %d: rel l2 %.3g, rel max %.3g" % (what, b, rel, mx)
+
+
+def _cmp_vol(gpu, ref, tol=TOL, what=""):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    rel = np.linalg.norm(gpu - ref) / np.linalg.norm(ref)
+    mx = np.abs(gpu - ref).max() / np.abs(ref).max()
+    assert rel <= tol and mx <= tol, "%s: rel l2 %.3g, rel max %.3g" % (what, rel, mx)
+
+
+ODD = syn.Geometry(29, 41, 37, 0.9, 1.1, 1.0, 50, 33, 1.7, 1.9, 400.0, 900.0, 12,
+                   angles=[0.0, np.pi / 4, np.pi / 2, np.pi, 3 * np.pi / 2, 0.3, 1.7, 2.9, 4.0, 5.5, 0.05, 6.2])
+
+
+def test_forward_odd_sizes_axis_aligned_views(fbl, orc):
+    g = ODD
+    print("case forward ODD", flush=True)
+    x = syn.random_volume(g, 3)
+    views = np.array([0, 1, 2, 3, 4, 7, 10, 11], dtype=np.int32)
+    ref = orc.forward(g, x.astype(np.float64), views)
+    with fbl.Plan(g) as plan:
+        y = fbl.fb_lisa_forward(plan, _t(x), views).cpu().numpy()
+    _cmp_views(y, ref, what="forward")
+
+
+def test_forward_residual_and_loss(fbl, orc):
+    import torch
+    g = ODD
+    x = syn.random_volume(g, 4)
+    b = syn.random_projections(g, g.n_views, 5, scale=2.0)
+    views = np.array([5, 2, 9], dtype=np.int32)
+    r_ref = orc.forward(g, x.astype(np.float64), views) - b.astype(np.float64)[views]
+    f_ref = g.n_views / (2.0 * len(views)) * float(np.sum(r_ref ** 2))
+    with fbl.Plan(g, max_batch=5) as plan:
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        r = fbl.fb_lisa_forward(plan, _t(x), views, _t(b), loss=loss).cpu().numpy()
+        f_gpu = float(loss.item())
+        # repeat: the FP64 reduction order is fixed
+        loss2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+        fbl.fb_lisa_forward(plan, _t(x), views, _t(b), loss=loss2)
+        assert loss2.item() == f_gpu
+    _cmp_views(r, r_ref, what="residual")
+    assert f_gpu == pytest.approx(f_ref, rel=TOL)
+
+
+def test_forward_c1_phantom_all_rays(fbl, orc):
+    g = syn.config_geometry("c1")
+    _, xt = syn.phantom(g, 10, seed=1000)
+    x32 = xt.astype(np.float32)
+    views = syn.view_permutations(g.n_views, 1, seed=1002)[0][:6]
+    ref = orc.forward(g, x32.astype(np.float64), views)
+    with fbl.Plan(g) as plan:
+        y = fbl.fb_lisa_forward(plan, _t(x32), views).cpu().numpy()
+    _cmp_views(y, ref, what="forward c1")
+
+
+def test_backproject_odd_sizes(fbl, orc):
+    g = ODD
+    rng = np.random.default_rng(6)
+    views = np.array([0, 1, 2, 3, 4, 7, 10], dtype=np.int32)
+    r = rng.standard_normal((len(views), g.nv, g.nu)).astype(np.float32)
+    ref = g.n_views / len(views) * orc.backproject(g, r.astype(np.float64), views)
+    with fbl.Plan(g) as plan:
+        gg = fbl.fb_lisa_backproject(plan, _t(r), views).cpu().numpy()
+        gg2 = fbl.fb_lisa_backproject(plan, _t(r), views).cpu().numpy()
+    assert np.array_equal(gg, gg2)  # no atomics: bitwise repeatable
+    _cmp_vol(gg, ref, what="backprojection")
+
+
+def test_backproject_c1_all_voxels(fbl, orc):
+    g = syn.config_geometry("c1")
+    rng = np.random.default_rng(7)
+    views = syn.view_permutations(g.n_views, 1, seed=7)[0][:6]
+    r = rng.standard_normal((len(views), g.nv, g.nu)).astype(np.float32)
+    ref = 1.7 * orc.backproject(g, r.astype(np.float64), views)
+    with fbl.Plan(g, max_batch=6) as plan:
+        gg = fbl.fb_lisa_backproject(plan, _t(r), views, grad_scale=1.7).cpu().numpy()
+    _cmp_vol(gg, ref, what="backprojection c1")
+
+
+def test_adjoint_identity_on_gpu(fbl):
+    import torch
+    g = syn.Geometry(40, 36, 30, 1.0, 1.0, 1.0, 60, 44, 1.4, 1.4, 400.0, 800.0, 16)
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal(g.vol_shape).astype(np.float32)
+    views = np.arange(0, 16, 3, dtype=np.int32)
+    y = rng.standard_normal((len(views), g.nv, g.nu)).astype(np.float32)
+    with fbl.Plan(g) as plan:
+        ax = fbl.fb_lisa_forward(plan, _t(x), views).double()
+        aty = fbl.fb_lisa_backproject(plan, _t(y), views, grad_scale=1.0).double()
+        lhs = float(torch.sum(ax * _t(y).double()))
+        rhs = float(torch.sum(_t(x).double() * aty))
+    assert lhs == pytest.approx(rhs, rel=1e-5)
+
+
+def test_explicit_matrix_8cubed(fbl, orc):
+    # Columns of A by GPU forward projection of unit voxels, rows by GPU backprojection
+    # of unit rays: both equal the oracle's explicit A to FP32 accuracy.
+    import torch
+    g = syn.tiny_geometry(n=8, det=12, views=16)
+    views = np.arange(16, dtype=np.int32)
+    A = orc.assemble_matrix(g, views)
+    with fbl.Plan(g) as plan:
+        e = torch.zeros(g.vol_shape, dtype=torch.float32, device="cuda")
+        cols = []
+        for i in range(g.d):
+            e.view(-1).zero_()
+            e.view(-1)[i] = 1.0
+            cols.append(fbl.fb_lisa_forward(plan, e, views).reshape(-1).cpu().numpy())
+        A_fp = np.stack(cols, axis=1)
+        rows = []
+        er = torch.zeros((16, g.nv, g.nu), dtype=torch.float32, device="cuda")
+        for i in range(0, 16 * g.n_p, 7):     # every 7th ray (a third of the rows)
+            er.view(-1).zero_()
+            er.view(-1)[i] = 1.0
+            rows.append((i, fbl.fb_lisa_backproject(plan, er, views, grad_scale=1.0).reshape(-1).cpu().numpy()))
+    scale = np.abs(A).max()
+    assert np.abs(A_fp - A).max() <= 1e-6 * scale
+    for i, row in rows:
+        assert np.abs(row - A[i]).max() <= 1e-6 * scale, i
+
+
+def test_step_parity(fbl, orc):
+    import torch
+    g = ODD
+    rng = np.random.default_rng(9)
+    x = rng.uniform(0, 0.03, g.vol_shape).astype(np.float32)
+    x[rng.random(g.vol_shape) < 0.2] = 0.0
+    grad = rng.standard_normal(g.vol_shape).astype(np.float32) * 3.0
+    with fbl.Plan(g) as plan:
+        for alpha, mu, lo, hi in ((1e-3, 0.0, 0.0, math.inf), (2.5e-3, 0.7, 0.0, 0.03), (1e-4, 2.0, 0.001, 0.025)):
+            red = torch.zeros(3, dtype=torch.float64, device="cuda")
+            xb, red = fbl.fb_lisa_step(plan, _t(x), _t(grad), alpha, mu, lo, hi, red=red)
+            xb = xb.cpu().numpy()
+            red = red.cpu().numpy()
+            xr, inner, sq, gg = orc.prox_step(x, grad, alpha, mu, lo, hi, storage=np.float32)
+            ulp = np.spacing(np.abs(xr).astype(np.float32)).astype(np.float64)
+            assert np.all(np.abs(xb.astype(np.float64) - xr) <= ulp)
+            frac_exact = np.mean(xb.astype(np.float64) == xr)
+            assert frac_exact > 0.999
+            assert red[0] == pytest.approx(inner, rel=1e-9)
+            assert red[1] == pytest.approx(sq, rel=1e-9)
+            assert red[2] == pytest.approx(gg, rel=1e-12)
+
+
+def test_chunked_batches_and_duplicates(fbl, orc):
+    # more views than one launch carries (256), duplicates and B = 1
+    g = syn.Geometry(12, 10, 8, 1.0, 1.0, 1.0, 16, 12, 1.5, 1.5, 300.0, 600.0, 300)
+    rng = np.random.default_rng(10)
+    x = rng.uniform(0, 1, g.vol_shape).astype(np.float32)
+    views = rng.integers(0, 300, 290).astype(np.int32)
+    views[5] = views[4]
+    r = rng.standard_normal((len(views), g.nv, g.nu)).astype(np.float32)
+    y_ref = orc.forward(g, x.astype(np.float64), views)
+    g_ref = orc.backproject(g, r.astype(np.float64), views)
+    with fbl.Plan(g) as plan:
+        y = fbl.fb_lisa_forward(plan, _t(x), views).cpu().numpy()
+        gg = fbl.fb_lisa_backproject(plan, _t(r), views, grad_scale=1.0).cpu().numpy()
+        y1 = fbl.fb_lisa_forward(plan, _t(x), views[:1]).cpu().numpy()
+    _cmp_views(y, y_ref, what="forward chunked")
+    assert np.array_equal(y[4], y[5])
+    _cmp_vol(gg, g_ref, what="backprojection chunked")
+    assert np.array_equal(y1[0], y[0])
+
+
+def test_host_checks_launch_nothing(fbl):
+    import torch
+    g = syn.tiny_geometry(n=8, det=12, views=16)
+    with fbl.Plan(g, max_batch=4) as plan:
+        x = torch.zeros(g.vol_shape, dtype=torch.float32, device="cuda")
+        with pytest.raises(fbl.FblError) as e:
+            fbl.fb_lisa_forward(plan, x, [0, 1, 2, 3, 4])
+        assert e.value.code == 3
+        with pytest.raises(fbl.FblError) as e:
+            fbl.fb_lisa_forward(plan, x, [16])
+        assert e.value.code == 3
+        with pytest.raises(fbl.FblError) as e:
+            fbl.fb_lisa_step(plan, x, torch.zeros_like(x), alpha=-1.0)
+        assert e.value.code == 1
+        with pytest.raises(fbl.FblError) as e:
+            fbl.fb_lisa_step(plan, x, torch.zeros_like(x), alpha=1.0, lo=0.5, hi=0.1)
+        assert e.value.code == 1
+    with pytest.raises(fbl.FblError) as e:
+        fbl.Plan(g, max_batch=17)
+    assert e.value.code == 3
+    with pytest.raises(fbl.FblError) as e:
+        fbl.Plan(g, vol_dtype="f32", proj_dtype="f32", max_batch=0)
+    assert e.value.code == 3
+
+
+@pytest.mark.parametrize("cfg", ["c2"])
+def test_full_size_sampled_parity(fbl, orc, cfg):
+    # Full-size geometry and the batch size the benchmark times; rays and voxels are
+    # sampled because the oracle evaluates them one by one.
+    import torch
+    g = syn.config_geometry(cfg)
+    c = syn.CONFIGS[cfg]
+    print("case full-size", cfg, flush=True)
+    ells, xt = syn.phantom(g, c["k"], seed=2000, hi=c["hi"], sub=2)
+    x32 = xt.astype(np.float32)
+    views = syn.view_permutations(g.n_views, 1, seed=2002)[0][:c["batch"]]
+    rng = np.random.default_rng(11)
+    with fbl.Plan(g, max_batch=c["batch"]) as plan:
+        xd = _t(x32)
+        y = fbl.fb_lisa_forward(plan, xd, views).cpu().numpy()
+        r = rng.standard_normal((len(views), g.nv, g.nu)).astype(np.float32)
+        gg = fbl.fb_lisa_backproject(plan, _t(r), views, grad_scale=1.0).cpu().numpy()
+    nr = 3000
+    rays = np.stack([rng.integers(0, len(views), nr), rng.integers(0, g.nv, nr), rng.integers(0, g.nu, nr)], 1)
+    rays_v = rays.copy()
+    rays_v[:, 0] = views[rays[:, 0]]
+    ref = orc.forward_rays(g, x32.astype(np.float64), rays_v)
+    got = y[rays[:, 0], rays[:, 1], rays[:, 2]].astype(np.float64)
+    scale = np.abs(ref).max()
+    assert scale > 0
+    assert np.abs(got - ref).max() <= TOL * scale
+    assert np.linalg.norm(got - ref) <= TOL * np.linalg.norm(ref)
+    # voxels: inside the field of view and at the volume's edges and corners
+    nvx = 96
+    vox = rng.integers(0, g.d, nvx)
+    vox[:8] = [0, g.nx - 1, g.nx * (g.ny - 1), g.d - 1, g.d // 2, g.d // 2 + 1, g.d // 2 + g.nx, g.d // 3]
+    gref = orc.backproject_voxels(g, r.astype(np.float64), views, vox)
+    ggot = gg.reshape(-1)[vox].astype(np.float64)
+    gscale = np.abs(gref).max()
+    assert gscale > 0
+    assert np.abs(ggot - gref).max() <= TOL * gscale
