@@ -79,15 +79,21 @@ struct fbl_plan {
     double *d_partials;           // FP64 per-block partial sums
     int64_t n_partials;
     float *d_rw;                  // [max_batch][nv][nu] weighted residual for the backprojection
+    void *d_xt;                   // [nz][nx][ny] y-fastest copy of the forward's input volume
+    unsigned char *view_axis0;    // host, per view: 1 if some column marches x = const slices
     int fp_blocks_per_view;       // forward launch shape
+    int fp_line;                  // per-thread LDS line length of the forward (16, 32 or 64)
 };
 
 namespace fbl {
 
 // Launch functions (stream-ordered, no synchronisation).  Each returns hipSuccess or the
 // launch error.
+hipError_t launch_transpose(const fbl_plan *p, const void *x, hipStream_t st);
 hipError_t launch_forward(const fbl_plan *p, const void *x, const ViewList &vl, int nb, int first,
                           const void *b, float *y, bool want_loss, hipStream_t st);
+int forward_blocks_per_view(const Geo &g);
+int forward_rows_per_thread();
 hipError_t launch_finalize_sum(double *partials, int64_t n, int ncomp, double scale, double *out,
                                hipStream_t st);
 hipError_t launch_prescale(const fbl_plan *p, const float *r, const ViewList &vl, int nb, int first,

@@ -1,4 +1,18 @@
 // Forward projection A_N x (Joseph, bilinear) with the residual and FP64 loss epilogue.
+//
+// Structure on gfx950.  All rays of one detector column share their dominant axis,
+// the slice plane they cross and their horizontal index coordinate xi on it, so the
+// bilinear sample factors into one horizontal interpolation of the slice's z-line at xi
+// (shared by every row of the column) and one vertical interpolation per ray.
+//   - A thread owns one column and kRows consecutive rows; a wavefront spans 64
+//     adjacent columns, so the horizontal tap pairs it loads are contiguous in memory
+//     (x-fastest volume for views whose slices are y = const, a y-fastest transposed
+//     copy for views whose slices are x = const).
+//   - Per slice the thread interpolates the z-range its rays cover into a private LDS
+//     line (interleaved [k][thread] so the 64 lanes never conflict), then each ray
+//     reads its two vertical taps with one ds_read2st64 and does one lerp.
+//   - Ray positions are refreshed in FP64 every kChunk slices and stepped in FP32
+//     inside the chunk; per-chunk FP32 partial sums keep the 256-1024-term sums accurate.
 #include "common.h"
 #include "device_util.h"
 
@@ -6,77 +20,224 @@ namespace fbl {
 
 namespace {
 
-constexpr int kTileU = 64;   // one wavefront spans 64 adjacent detector columns of a row
-constexpr int kTileV = 4;    // four rows per 256-thread block
-constexpr int kChunk = 16;   // slices per FP64 position refresh and per FP32 partial sum
+constexpr int kCols = 64;     // columns per block (one per lane)
+constexpr int kWaves = 4;     // row groups per block (one per wavefront)
+constexpr int kRows = 16;     // rays (rows) per thread
+constexpr int kChunk = 16;    // slices per FP64 position refresh and per FP32 partial sum
+constexpr int kThreads = kCols * kWaves;
 
+// Horizontal pair of taps (p, p+1) of one z-row: both at consecutive addresses.
 template <typename TV>
-__device__ __forceinline__ float tap(const TV *__restrict__ x, int base, int ib, int jz, int nb, int nz, int sb,
-                                     int sz)
+__device__ __forceinline__ void load_pair(const TV *__restrict__ base, int64_t off, float &a, float &b)
 {
-    return ((unsigned)ib < (unsigned)nb && (unsigned)jz < (unsigned)nz) ? to_f32(x[base + ib * sb + jz * sz])
-                                                                         : 0.0f;
+    a = to_f32(base[off]);
+    b = to_f32(base[off + 1]);
 }
 
-template <typename TV, typename TB>
-__global__ __launch_bounds__(256) void fp_kernel(const TV *__restrict__ x, Geo geo, DeviceTables tab, ViewList vl,
-                                                 int first, const TB *__restrict__ b, float *__restrict__ y,
-                                                 double *__restrict__ partials, int blocks_per_view, int want_loss)
+// Per-slice horizontal state of a thread: tap column p with weights (wa, wb), and the
+// z-line it fills: line entry kk holds z = kz + kk; ka is the line origin in the
+// thread's ray coordinates.
+struct SliceState {
+    int64_t row;     // element offset of (slice, p, z = kz)
+    float wa, wb;
+    int ka, kz;
+    bool inside;     // z = kz .. kz+KB-1 all inside the volume
+};
+
+template <typename TB, int KB>
+struct LineRegs {
+    float a[KB], b[KB];
+};
+
+template <typename TV, typename TB, int KB>
+__global__ __launch_bounds__(kThreads) void fp_kernel(const TV *__restrict__ x, const TV *__restrict__ xt, Geo geo,
+                                                      DeviceTables tab, ViewList vl, int first,
+                                                      const TB *__restrict__ b, float *__restrict__ y,
+                                                      double *__restrict__ partials, int blocks_per_view,
+                                                      int want_loss)
 {
+    __shared__ float line[KB * kThreads];
     __shared__ double red[4];
     const int bi = blockIdx.y;
     const int view = vl.v[bi];
-    const int tiles_u = (geo.nu + kTileU - 1) / kTileU;
-    const int iu = (blockIdx.x % tiles_u) * kTileU + (threadIdx.x & (kTileU - 1));
-    const int iv = (blockIdx.x / tiles_u) * kTileV + (threadIdx.x / kTileU);
-    double sq = 0.0;
-    if (iu < geo.nu && iv < geo.nv) {
-        const ColParam cp = tab.col[(int64_t)view * geo.nu + iu];
-        const double V = tab.rowV[iv];
-        // slices along x (axis 0) or y (axis 1); xi runs along the other horizontal axis
-        const int na = cp.axis == 0 ? geo.nx : geo.ny;
-        const int nb = cp.axis == 0 ? geo.ny : geo.nx;
-        const int sa = cp.axis == 0 ? 1 : geo.nx;
-        const int sb = cp.axis == 0 ? geo.nx : 1;
-        const int sz = geo.nx * geo.ny;
-        const float xs = (float)cp.xi1;          // xi per slice
-        const float es = (float)(cp.t1 * V);     // eta per slice
-        float acc = 0.0f;
-        for (int m0 = 0; m0 < na; m0 += kChunk) {
-            // FP64 position at the chunk's first slice, split into index + FP32 offset
-            const double xb = fma((double)m0, cp.xi1, cp.xi0);
-            const double eb = fma(fma((double)m0, cp.t1, cp.t0), V, geo.cz);
-            const double fxb = floor(xb), feb = floor(eb);
-            const int ib = (int)fxb, jb = (int)feb;
-            const float xf = (float)(xb - fxb), ef = (float)(eb - feb);
-            const int m1 = min(m0 + kChunk, na);
-            float part = 0.0f;
-            for (int m = m0; m < m1; ++m) {
-                const float fl = (float)(m - m0);
-                const float xl = fmaf(fl, xs, xf), el = fmaf(fl, es, ef);
-                const float fxl = floorf(xl), fel = floorf(el);
-                const int i0 = ib + (int)fxl, j0 = jb + (int)fel;
-                const float ax = xl - fxl, ay = el - fel;
-                const int base = m * sa;
-                const float t00 = tap(x, base, i0, j0, nb, geo.nz, sb, sz);
-                const float t10 = tap(x, base, i0 + 1, j0, nb, geo.nz, sb, sz);
-                const float t01 = tap(x, base, i0, j0 + 1, nb, geo.nz, sb, sz);
-                const float t11 = tap(x, base, i0 + 1, j0 + 1, nb, geo.nz, sb, sz);
-                const float lo = fmaf(ax, t10 - t00, t00);
-                const float hi = fmaf(ax, t11 - t01, t01);
-                part += fmaf(ay, hi - lo, lo);
+    const int tiles_u = (geo.nu + kCols - 1) / kCols;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kCols - 1), wave = tid / kCols;
+    const int c = (blockIdx.x % tiles_u) * kCols + lane;
+    const int r0 = ((blockIdx.x / tiles_u) * kWaves + wave) * kRows;
+    const int nrows = max(0, min(kRows, geo.nv - r0));
+    const bool active = c < geo.nu && nrows > 0;
+
+    float acc[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) acc[r] = 0.0f;
+
+    // Inactive lanes (past the detector edge) run the loop on a clamped column and row
+    // so that every lane takes part in the wave-wide decisions; their sums are dropped.
+    const int cc = min(c, geo.nu - 1);
+    const int rr0 = min(r0, geo.nv - 1);
+    const ColParam cp = tab.col[(int64_t)view * geo.nu + cc];
+    // slices along x (axis 0, read from the transposed copy) or y (axis 1)
+    const int na = cp.axis == 0 ? geo.nx : geo.ny;
+    const int nb = cp.axis == 0 ? geo.ny : geo.nx;
+    const TV *__restrict__ vol = cp.axis == 0 ? xt : x;
+    const int64_t zstride = (int64_t)geo.nx * geo.ny;
+    const int64_t sstride = cp.axis == 0 ? geo.ny : geo.nx;
+    const double *__restrict__ Vrow = tab.rowV;
+    const float xs = (float)cp.xi1;
+    // per-ray eta slope per slice; row values are re-read (cached) at each refresh
+    float es[kRows], eb[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) es[r] = (float)(cp.t1 * Vrow[min(rr0 + r, geo.nv - 1)]);
+    float *__restrict__ my = line + tid;
+    // the longest slice march in the block decides the trip count of every lane
+    int na_max = na;
+    for (int off = 32; off > 0; off >>= 1) na_max = max(na_max, __shfl_xor(na_max, off, 64));
+
+    for (int m0 = 0; m0 < na_max; m0 += kChunk) {
+        const int sc = min(kChunk, na - m0);   // slices of this lane in the chunk (may be <= 0)
+        // FP64 positions at the chunk's first slice.  Integer bases are taken below the
+        // smallest value reached in the chunk, so all in-chunk offsets are >= 0 and
+        // truncation equals floor.
+        const double xb = fma((double)m0, cp.xi1, cp.xi0);
+        const double xmin = fmin(xb, xb + (double)(kChunk - 1) * cp.xi1);
+        const int ib = (int)floor(xmin) - 1;
+        const float xf = (float)(xb - (double)ib);
+        const double tb = fma((double)m0, cp.t1, cp.t0);
+        const double e0 = fma(tb, Vrow[rr0], geo.cz);
+        const double emin = fmin(e0, e0 + (double)(kChunk - 1) * cp.t1 * Vrow[rr0]);
+        const int k0 = (int)floor(emin) - 1;
+#pragma unroll
+        for (int r = 0; r < kRows; ++r)
+            eb[r] = (float)(fma(tb, Vrow[min(rr0 + r, geo.nv - 1)], geo.cz) - (double)k0);
+        float part[kRows];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) part[r] = 0.0f;
+
+        auto slice_state = [&](int s) {
+            SliceState S;
+            const float fl = (float)s;
+            const float xl = fmaf(fl, xs, xf);
+            const int i0 = ib + (int)xl;
+            const float ax = __builtin_amdgcn_fractf(xl);
+            int p = i0;
+            S.wa = 1.0f - ax;
+            S.wb = ax;
+            if (i0 < 0 || i0 > nb - 2) {
+                if (i0 == -1) { p = 0; S.wa = ax; S.wb = 0.0f; }
+                else if (i0 == nb - 1) { p = nb - 2; S.wa = 0.0f; S.wb = 1.0f - ax; }
+                else { p = 0; S.wa = 0.0f; S.wb = 0.0f; }
             }
-            acc += part;
+            const float ef = fmaf(fl, es[0], eb[0]);
+            S.ka = (int)(ef - 1e-3f);
+            S.kz = k0 + S.ka;
+            S.inside = S.kz >= 0 && S.kz + KB <= geo.nz;
+            // a lane whose march ended (fewer slices than the block's longest) keeps
+            // addressing its last slice; its ray pass is skipped
+            S.row = (int64_t)min(m0 + s, na - 1) * sstride + p + (int64_t)S.kz * zstride;
+            return S;
+        };
+        auto load_line = [&](const SliceState &S, LineRegs<TB, KB> &L) {
+            const TV *__restrict__ q = vol + S.row;
+#pragma unroll
+            for (int kk = 0; kk < KB; ++kk) {
+                L.a[kk] = to_f32(q[0]);
+                L.b[kk] = to_f32(q[1]);
+                q += zstride;
+            }
+        };
+
+        LineRegs<TB, KB> L;
+        SliceState P = slice_state(0);
+        bool fastP = __all(P.inside);
+        if (fastP) load_line(P, L);
+        for (int s = 0; s < kChunk; ++s) {
+            // horizontal interpolation of the z-line at the column's xi
+            if (fastP) {
+#pragma unroll
+                for (int kk = 0; kk < KB; ++kk) my[kk * kThreads] = fmaf(P.wb, L.b[kk], P.wa * L.a[kk]);
+            } else {
+                for (int kk = 0; kk < KB; ++kk) {
+                    const int k = P.kz + kk;
+                    float v = 0.0f;
+                    if ((unsigned)k < (unsigned)geo.nz) {
+                        const TV *__restrict__ q = vol + (P.row + (int64_t)kk * zstride);
+                        v = fmaf(P.wb, to_f32(q[1]), P.wa * to_f32(q[0]));
+                    }
+                    my[kk * kThreads] = v;
+                }
+            }
+            // prefetch the next slice's taps before the ray pass of this one
+            SliceState Q = P;
+            bool fastQ = false;
+            if (s + 1 < kChunk) {
+                Q = slice_state(s + 1);
+                fastQ = __all(Q.inside);
+                if (fastQ) load_line(Q, L);
+            }
+            // vertical interpolation per ray from the thread's line
+            if (s < sc) {
+                const float fl = (float)s;
+                float *__restrict__ base = my - P.ka * kThreads;
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) {
+                    const float e = fmaf(fl, es[r], eb[r]);
+                    const int j = (int)e;
+                    const float ay = __builtin_amdgcn_fractf(e);
+                    const float t0 = base[j * kThreads];
+                    const float t1 = base[(j + 1) * kThreads];
+                    part[r] += fmaf(ay, t1 - t0, t0);
+                }
+            }
+            P = Q;
+            fastP = fastQ;
         }
-        const float w = cp.wa * sqrtf(cp.l2 + tab.rowV2[iv]);
-        float val = w * acc;
-        if (b) val -= to_f32(b[(int64_t)view * geo.np + (int64_t)iv * geo.nu + iu]);
-        y[(int64_t)(first + bi) * geo.np + (int64_t)iv * geo.nu + iu] = val;
-        sq = (double)val * (double)val;
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) acc[r] += part[r];
+    }
+
+    double sq = 0.0;
+    if (active) {
+        const int64_t row0 = (int64_t)(first + bi) * geo.np;
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            if (r < nrows) {
+                const int iv = r0 + r;
+                const float w = cp.wa * sqrtf(cp.l2 + tab.rowV2[iv]);
+                float val = w * acc[r];
+                if (b) val -= to_f32(b[(int64_t)view * geo.np + (int64_t)iv * geo.nu + c]);
+                y[row0 + (int64_t)iv * geo.nu + c] = val;
+                sq += (double)val * (double)val;
+            }
+        }
     }
     if (want_loss) {
         const double s = block_sum_256(sq, red);
-        if (threadIdx.x == 0) partials[(int64_t)(first + bi) * blocks_per_view + blockIdx.x] = s;
+        if (tid == 0) partials[(int64_t)(first + bi) * blocks_per_view + blockIdx.x] = s;
+    }
+}
+
+// xt[k][i][j] = x[k][j][i]: y-fastest copy read by views whose slices are x = const.
+template <typename TV>
+__global__ __launch_bounds__(256) void transpose_xy_kernel(const TV *__restrict__ x, TV *__restrict__ xt, int nx,
+                                                           int ny, int nz)
+{
+    __shared__ TV tile[32][33];
+    const int tiles_x = (nx + 31) / 32;
+    const int ti = blockIdx.x % tiles_x, tj = blockIdx.x / tiles_x;
+    const int k = blockIdx.y;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    const int64_t slab = (int64_t)k * nx * ny;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = tj * 32 + ty + 8 * q, i = ti * 32 + tx;
+        if (i < nx && j < ny) tile[ty + 8 * q][tx] = x[slab + (int64_t)j * nx + i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = ti * 32 + ty + 8 * q, j = tj * 32 + tx;
+        if (i < nx && j < ny) xt[slab + (int64_t)i * ny + j] = tile[tx][ty + 8 * q];
     }
 }
 
@@ -96,18 +257,52 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double *__restrict_
 
 int forward_blocks_per_view(const Geo &g)
 {
-    return ((g.nu + kTileU - 1) / kTileU) * ((g.nv + kTileV - 1) / kTileV);
+    return ((g.nu + kCols - 1) / kCols) * ((g.nv + kWaves * kRows - 1) / (kWaves * kRows));
+}
+
+int forward_rows_per_thread() { return kRows; }
+
+template <typename TV, typename TB, int KB>
+static hipError_t launch_fp_kb(const fbl_plan *p, const void *x, const void *xt, const ViewList &vl, int nb,
+                               int first, const void *b, float *y, bool want_loss, hipStream_t st)
+{
+    DeviceTables tab{p->d_col, p->d_rowV, p->d_rowV2, p->d_view};
+    dim3 grid(p->fp_blocks_per_view, nb);
+    hipLaunchKernelGGL((fp_kernel<TV, TB, KB>), grid, dim3(kThreads), 0, st, (const TV *)x, (const TV *)xt, p->geo,
+                       tab, vl, first, (const TB *)b, y, p->d_partials, p->fp_blocks_per_view, want_loss ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <typename TV>
+static hipError_t launch_transpose_t(const fbl_plan *p, const void *x, hipStream_t st)
+{
+    const int tiles = ((p->geo.nx + 31) / 32) * ((p->geo.ny + 31) / 32);
+    hipLaunchKernelGGL((transpose_xy_kernel<TV>), dim3(tiles, p->geo.nz), dim3(256), 0, st, (const TV *)x,
+                       (TV *)p->d_xt, p->geo.nx, p->geo.ny, p->geo.nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const fbl_plan *p, const void *x, hipStream_t st)
+{
+    switch (p->vol_dtype) {
+    case FBL_F32: return launch_transpose_t<float>(p, x, st);
+    case FBL_BF16: return launch_transpose_t<__hip_bfloat16>(p, x, st);
+    default: return launch_transpose_t<__half>(p, x, st);
+    }
 }
 
 template <typename TV, typename TB>
 static hipError_t launch_fp_t(const fbl_plan *p, const void *x, const ViewList &vl, int nb, int first,
                               const void *b, float *y, bool want_loss, hipStream_t st)
 {
-    DeviceTables tab{p->d_col, p->d_rowV, p->d_rowV2, p->d_view};
-    dim3 grid(p->fp_blocks_per_view, nb);
-    hipLaunchKernelGGL((fp_kernel<TV, TB>), grid, dim3(256), 0, st, (const TV *)x, p->geo, tab, vl, first,
-                       (const TB *)b, y, p->d_partials, p->fp_blocks_per_view, want_loss ? 1 : 0);
-    return hipGetLastError();
+    const void *xt = p->d_xt;
+    switch (p->fp_line) {
+    case 12: return launch_fp_kb<TV, TB, 12>(p, x, xt, vl, nb, first, b, y, want_loss, st);
+    case 16: return launch_fp_kb<TV, TB, 16>(p, x, xt, vl, nb, first, b, y, want_loss, st);
+    case 24: return launch_fp_kb<TV, TB, 24>(p, x, xt, vl, nb, first, b, y, want_loss, st);
+    case 32: return launch_fp_kb<TV, TB, 32>(p, x, xt, vl, nb, first, b, y, want_loss, st);
+    default: return launch_fp_kb<TV, TB, 48>(p, x, xt, vl, nb, first, b, y, want_loss, st);
+    }
 }
 
 hipError_t launch_forward(const fbl_plan *p, const void *x, const ViewList &vl, int nb, int first, const void *b,

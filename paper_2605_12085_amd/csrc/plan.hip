@@ -9,10 +9,6 @@
 
 #include "common.h"
 
-namespace fbl {
-int forward_blocks_per_view(const Geo &g);
-}
-
 using namespace fbl;
 
 namespace {
@@ -102,6 +98,8 @@ int check_geometry(const fbl_geometry *g)
         return fail(FBL_E_GEOMETRY, "every count must be >= 1 (nx=%lld ny=%lld nz=%lld nu=%lld nv=%lld n_views=%lld)",
                     (long long)g->nx, (long long)g->ny, (long long)g->nz, (long long)g->nu, (long long)g->nv,
                     (long long)g->n_views);
+    if (g->nx < 2 || g->ny < 2)
+        return fail(FBL_E_GEOMETRY, "nx and ny must be >= 2 (the in-slice interpolation needs two taps)");
     if (g->nx > (1 << 24) || g->ny > (1 << 24) || g->nz > (1 << 24) || g->nu > (1 << 24) || g->nv > (1 << 24))
         return fail(FBL_E_GEOMETRY, "a dimension exceeds 2^24");
     if ((double)g->nx * (double)g->ny * (double)g->nz >= 2147483648.0)
@@ -161,8 +159,10 @@ void free_plan(fbl_plan *p)
     (void)hipFree(p->d_view);
     (void)hipFree(p->d_partials);
     (void)hipFree(p->d_rw);
+    (void)hipFree(p->d_xt);
     if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);
     delete[] p->angles_host;
+    delete[] p->view_axis0;
     delete p;
 }
 
@@ -246,11 +246,21 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
     G.np = g->nu * g->nv;
 
     std::vector<ColParam> col((size_t)g->n_views * (size_t)g->nu);
-    for (int64_t v = 0; v < g->n_views; ++v)
+    p->view_axis0 = new unsigned char[g->n_views];
+    double tau_max = 0.0;
+    for (int64_t v = 0; v < g->n_views; ++v) {
+        p->view_axis0[v] = 0;
         for (int64_t iu = 0; iu < g->nu; ++iu) {
             const ColumnGeom cg = column_geom(p->geom, v, iu);
             ColParam &cp = col[(size_t)v * (size_t)g->nu + (size_t)iu];
             const int a = std::fabs(cg.D[0]) >= std::fabs(cg.D[1]) ? 0 : 1;
+            if (a == 0) p->view_axis0[v] = 1;
+            {
+                // largest ray parameter on the first and last slice (tau is affine in m)
+                const double na = (double)(a == 0 ? g->nx : g->ny);
+                const double ta = (0.0 - cg.P[a]) / cg.D[a], tb = (na - 1.0 - cg.P[a]) / cg.D[a];
+                tau_max = std::fmax(tau_max, std::fmax(ta, tb));
+            }
             const int b = 1 - a;
             const double ha = a == 0 ? g->hx : g->hy;
             // slice m is crossed at t = (m - P_a)/D_a; there xi = P_b + t D_b
@@ -266,6 +276,24 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
             cp.axis = a;
             cp.pad = 0;
         }
+    }
+    // Forward: a thread's rows span at most tau_max * (rows-1) * dv/hz voxels in z on a
+    // slice.  Its LDS line runs from floor(first - 1e-3) to floor(last) + 1, i.e. at most
+    // floor(span + 1e-3) + 3 entries; the bound below keeps a margin for FP32 rounding.
+    {
+        const double span = tau_max * (double)(forward_rows_per_thread() - 1) * (g->dv / g->hz);
+        const double need = std::floor(span + 0.01) + 3.0;
+        const int sizes[] = {12, 16, 24, 32, 48};
+        p->fp_line = 0;
+        for (int sz : sizes)
+            if (p->fp_line == 0 && need <= (double)sz) p->fp_line = sz;
+        if (p->fp_line == 0) {
+            free_plan(p);
+            return fail(FBL_E_GEOMETRY,
+                        "detector rows are too coarse for the voxel size: %d rows span %.1f voxels in z (max 45)",
+                        forward_rows_per_thread(), span);
+        }
+    }
     std::vector<double> rowV((size_t)g->nv);
     std::vector<float> rowV2((size_t)g->nv);
     for (int64_t iv = 0; iv < g->nv; ++iv) {
@@ -293,6 +321,8 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
     }
     e = hipMalloc((void **)&p->d_partials, (size_t)p->n_partials * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_rw, (size_t)max_batch * (size_t)G.np * sizeof(float));
+    if (e == hipSuccess)
+        e = hipMalloc(&p->d_xt, (size_t)g->nx * (size_t)g->ny * (size_t)g->nz * (vol_dtype == FBL_F32 ? 4u : 2u));
     if (e != hipSuccess) {
         free_plan(p);
         return fail(FBL_E_NOMEM, "hipMalloc of plan workspace: %s", hipGetErrorString(e));
@@ -313,6 +343,13 @@ int fb_lisa_forward(fbl_plan *p, const void *x, const int32_t *views, int32_t B,
         return fail(FBL_E_INVALID, "arrays must be 16-byte aligned and loss_dev 8-byte aligned");
     if (loss_dev && !std::isfinite(loss_scale)) return fail(FBL_E_INVALID, "loss_scale must be finite");
     hipStream_t st = (hipStream_t)stream;
+    bool need_xt = false;
+    for (int32_t k = 0; k < B; ++k) need_xt = need_xt || p->view_axis0[views[k]];
+    if (need_xt) {
+        // views that march x = const slices read a y-fastest copy of x
+        hipError_t e = launch_transpose(p, x, st);
+        if (e != hipSuccess) return hip_fail(e, "volume transpose launch");
+    }
     for (int first = 0; first < B; first += kViewsPerLaunch) {
         const int nb = B - first < kViewsPerLaunch ? B - first : kViewsPerLaunch;
         hipError_t e = launch_forward(p, x, chunk(views, first, nb), nb, first, b, y, loss_dev != nullptr, st);

@@ -158,10 +158,13 @@ def test_explicit_matrix_8cubed(fbl, orc):
             er.view(-1).zero_()
             er.view(-1)[i] = 1.0
             rows.append((i, fbl.fb_lisa_backproject(plan, er, views, grad_scale=1.0).reshape(-1).cpu().numpy()))
+    # entries are weights w*(1-a)(1-b); the kernels step positions in FP32 relative to an
+    # integer base up to ~20 voxels away (resolution ~2e-6 voxel), so an entry is exact to
+    # a few 1e-6 of the largest one
     scale = np.abs(A).max()
-    assert np.abs(A_fp - A).max() <= 1e-6 * scale
+    assert np.abs(A_fp - A).max() <= 4e-6 * scale
     for i, row in rows:
-        assert np.abs(row - A[i]).max() <= 1e-6 * scale, i
+        assert np.abs(row - A[i]).max() <= 4e-6 * scale, i
 
 
 def test_step_parity(fbl, orc):
