@@ -41,8 +41,9 @@ struct ColParam {
 // Per-view quantities used by the voxel-driven backprojection to find the detector
 // columns near a voxel: the projection u(p) = sdd (p.e_u)/(sod - p.n) of a point p.
 struct ViewParam {
-    float c, s;       // cos, sin of the view angle
-    float pad0, pad1;
+    float c, s;         // cos, sin of the view angle
+    int32_t axis_first; // dominant axis of column 0
+    int32_t split;      // first column with the other axis (nu if none); at most one change
 };
 
 struct Geo {
@@ -82,7 +83,9 @@ struct fbl_plan {
     void *d_xt;                   // [nz][nx][ny] y-fastest copy of the forward's input volume
     unsigned char *view_axis0;    // host, per view: 1 if some column marches x = const slices
     int fp_blocks_per_view;       // forward launch shape
-    int fp_line;                  // per-thread LDS line length of the forward (16, 32 or 64)
+    int fp_line;                  // per-thread LDS line length of the forward
+    int bp_pairs;                 // detector columns per slice the backprojection tile holds
+    int bp_cand;                  // detector rows examined per voxel in the z-profile gather
 };
 
 namespace fbl {
@@ -104,5 +107,6 @@ hipError_t launch_step(const fbl_plan *p, const void *x, const float *g, double 
                        double hi, void *xbar, int64_t *n_partials_used, hipStream_t st);
 
 int step_blocks(const fbl_plan *p);
+int backproject_tile();   // in-slice tile extent of the backprojection (voxels)
 
 }  // namespace fbl

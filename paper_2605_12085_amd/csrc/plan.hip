@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -247,7 +248,7 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
 
     std::vector<ColParam> col((size_t)g->n_views * (size_t)g->nu);
     p->view_axis0 = new unsigned char[g->n_views];
-    double tau_max = 0.0;
+    double tau_max = 0.0, tau_min = 1.0;
     for (int64_t v = 0; v < g->n_views; ++v) {
         p->view_axis0[v] = 0;
         for (int64_t iu = 0; iu < g->nu; ++iu) {
@@ -260,6 +261,7 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
                 const double na = (double)(a == 0 ? g->nx : g->ny);
                 const double ta = (0.0 - cg.P[a]) / cg.D[a], tb = (na - 1.0 - cg.P[a]) / cg.D[a];
                 tau_max = std::fmax(tau_max, std::fmax(ta, tb));
+                tau_min = std::fmin(tau_min, std::fmin(ta, tb));
             }
             const int b = 1 - a;
             const double ha = a == 0 ? g->hx : g->hy;
@@ -294,18 +296,95 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
                         forward_rows_per_thread(), span);
         }
     }
+    std::vector<ViewParam> vp((size_t)g->n_views);
+    for (int64_t v = 0; v < g->n_views; ++v) {
+        const double th = p->angles_host[v];
+        vp[(size_t)v].c = (float)std::cos(th);
+        vp[(size_t)v].s = (float)std::sin(th);
+        // columns change dominant axis at most once along a detector row
+        const ColParam *cv = &col[(size_t)v * (size_t)g->nu];
+        int split = (int)g->nu, changes = 0;
+        for (int64_t iu = 1; iu < g->nu; ++iu)
+            if (cv[iu].axis != cv[iu - 1].axis) {
+                if (changes == 0) split = (int)iu;
+                ++changes;
+            }
+        if (changes > 1) {
+            free_plan(p);
+            return fail(FBL_E_GEOMETRY, "view %lld: the detector row changes dominant axis %d times (fan too wide)",
+                        (long long)v, changes);
+        }
+        vp[(size_t)v].axis_first = cv[0].axis;
+        vp[(size_t)v].split = split;
+    }
+    // Backprojection: the largest number of detector columns crossing one slice of a tile
+    // (kernel arithmetic replayed in FP32 over every view, class, slice and tile), which
+    // sizes the tile's LDS pair table; and the number of detector rows within one voxel
+    // of a z-position, 2 / (row spacing in voxels) + 1, which sizes the profile gather.
+    {
+        const double rowz_min = tau_min * (g->dv / g->hz);
+        const double cand = std::floor(2.0 / rowz_min) + 2.0;
+        p->bp_cand = cand <= 4.0 ? 4 : cand <= 6.0 ? 6 : cand <= 8.0 ? 8 : 0;
+        if (p->bp_cand == 0) {
+            free_plan(p);
+            return fail(FBL_E_GEOMETRY, "detector rows are too fine for the voxel size (%.3f voxels apart, min 0.34)",
+                        rowz_min);
+        }
+        const int TQ = backproject_tile();
+        const float cxv = 0.5f * (float)(g->nx - 1), cyv = 0.5f * (float)(g->ny - 1);
+        const float fsod = (float)g->sod, fsdd = (float)g->sdd, fdu = (float)g->du, fcu = (float)(0.5 * (double)(g->nu - 1));
+        const float fhx = (float)g->hx, fhy = (float)g->hy;
+        auto col_of = [&](float c, float s, float X, float Y) {
+            const float lat = -X * s + Y * c;
+            const float dep = fsod - (X * c + Y * s);
+            return fsdd * lat / dep / fdu + fcu;
+        };
+        int max_n = 0;
+        for (int64_t v = 0; v < g->n_views; ++v) {
+            const float c = vp[(size_t)v].c, s = vp[(size_t)v].s;
+            for (int cls = 0; cls < 2; ++cls) {
+                const int axis = cls == 0 ? vp[(size_t)v].axis_first : 1 - vp[(size_t)v].axis_first;
+                const int cl0 = cls == 0 ? 0 : vp[(size_t)v].split;
+                const int cl1 = cls == 0 ? vp[(size_t)v].split - 1 : (int)g->nu - 1;
+                if (cl0 > cl1) continue;
+                const int na = (int)(axis == 0 ? g->nx : g->ny), nq = (int)(axis == 0 ? g->ny : g->nx);
+                for (int q0 = 0; q0 < nq; q0 += TQ)
+                    for (int mg = 0; mg < na; ++mg) {
+                        const float fm = (float)mg;
+                        float u0, u1;
+                        if (axis == 0) {
+                            const float X = (fm - cxv) * fhx;
+                            u0 = col_of(c, s, X, ((float)(q0 - 1) - cyv) * fhy);
+                            u1 = col_of(c, s, X, ((float)(q0 + TQ) - cyv) * fhy);
+                        } else {
+                            const float Y = (fm - cyv) * fhy;
+                            u0 = col_of(c, s, ((float)(q0 - 1) - cxv) * fhx, Y);
+                            u1 = col_of(c, s, ((float)(q0 + TQ) - cxv) * fhx, Y);
+                        }
+                        const int a = std::max(cl0, (int)std::floor(std::fmin(u0, u1)) - 1);
+                        const int b = std::min(cl1, (int)std::ceil(std::fmax(u0, u1)) + 1);
+                        max_n = std::max(max_n, b - a + 1);
+                    }
+            }
+        }
+        const int need = max_n + 1;   // one column of margin for FP contraction differences
+        const int sizes[] = {32, 48, 64};
+        p->bp_pairs = 0;
+        for (int sz : sizes)
+            if (p->bp_pairs == 0 && need <= sz) p->bp_pairs = sz;
+        if (p->bp_pairs == 0) {
+            free_plan(p);
+            return fail(FBL_E_GEOMETRY,
+                        "detector columns are too fine for the voxel size: %d columns cross one %d-voxel tile slice",
+                        max_n, TQ);
+        }
+    }
     std::vector<double> rowV((size_t)g->nv);
     std::vector<float> rowV2((size_t)g->nv);
     for (int64_t iv = 0; iv < g->nv; ++iv) {
         const double v = ((double)iv - 0.5 * (double)(g->nv - 1)) * g->dv;
         rowV[(size_t)iv] = v / g->hz;
         rowV2[(size_t)iv] = (float)(v * v);
-    }
-    std::vector<ViewParam> vp((size_t)g->n_views);
-    for (int64_t v = 0; v < g->n_views; ++v) {
-        const double th = p->angles_host[v];
-        vp[(size_t)v].c = (float)std::cos(th);
-        vp[(size_t)v].s = (float)std::sin(th);
     }
     p->fp_blocks_per_view = forward_blocks_per_view(G);
     const int64_t np_fp = (int64_t)max_batch * p->fp_blocks_per_view;
