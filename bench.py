@@ -96,6 +96,9 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2", help="workload (c1..c4); the default is the metric's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="counter-collection run: 3 forward, 1 backprojection, 1 step call of the workload, then "
+                         "a plain 512 MiB device copy whose FETCH_SIZE/WRITE_SIZE calibrate the counters")
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -124,6 +127,23 @@ def main(argv=None):
 
     b_dev = torch.from_numpy(b32).cuda()
     alpha0, beta = 1e-3, 0.5
+    if args.probe:
+        plan = fbl.Plan(g, max_batch=B)
+        x = torch.from_numpy(xt.astype(np.float32)).cuda()
+        views = perms[0][:B]
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            r = fbl.fb_lisa_forward(plan, x, views, b_dev, loss=loss)
+        gr = fbl.fb_lisa_backproject(plan, r, views)
+        fbl.fb_lisa_step(plan, x, gr, alpha0, 0.0, cfg["lo"], cfg["hi"])
+        torch.cuda.synchronize()
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": args.config, "copy_bytes": src.numel() * 4,
+                          "forward_bytes_model": B * (g.d * 4 + 4 * g.n_p)}), flush=True)
+        return 0
     run = fbl.FBLisa(g, b_dev, n0=B, epochs=cfg["epochs"], alpha0=alpha0, beta=beta, lo=cfg["lo"], hi=cfg["hi"],
                      time_calls=False)
     for k in range(args.warmup):

@@ -33,7 +33,7 @@ constexpr int kTK = 16;        // tile extent along z (voxels per thread)
 constexpr int kSP = 8;         // slices per pass (two passes cover the tile)
 constexpr int kThreads = 256;
 constexpr int kRowPad = 8;     // zero rows above and below the staged residual window
-constexpr int kWinRows = 64;   // staged rows per column (longer spans read global memory)
+constexpr int kWinRows = 48;   // staged rows per column (longer spans read global memory)
 
 // rw = grad_scale * w * r: the per-ray path length per slice folded into the residual.
 __global__ __launch_bounds__(256) void prescale_kernel(const float *__restrict__ r, Geo geo, DeviceTables tab,
@@ -62,7 +62,7 @@ __device__ __forceinline__ float column_of(const Geo &geo, const ViewParam &vp, 
 
 // z-profile of one (slice, column) pair: Z(kk) = sum_t hat(e_t - kk) * val(t), where row t
 // of the pair's source has e_t = a0 + rowz * t (eta relative to the tile's first z).  The
-// NC candidates of each kk start at the first row with e_t > kk - 1.
+// NC = ceil(2 / rowz) candidates of each kk start at the first row with e_t > kk - 1.
 template <int NC, typename Fetch>
 __device__ __forceinline__ void pair_profile(float a0, float rowz, int t_lo, int t_hi, Fetch fetch, float *zout,
                                              int zstride)
@@ -86,20 +86,19 @@ __device__ __forceinline__ void pair_profile(float a0, float rowz, int t_lo, int
 }
 
 template <int WP, int NC>
-__global__ __launch_bounds__(kThreads) void bp_kernel(const float *__restrict__ rw, Geo geo, DeviceTables tab,
+__global__ __launch_bounds__(kThreads, 3) void bp_kernel(const float *__restrict__ rw, Geo geo, DeviceTables tab,
                                                       ViewList vl, int nb, int first, int accumulate,
                                                       float *__restrict__ g)
 {
     constexpr int NPAIR = kSP * WP;
     constexpr int kWinCols = WP + 3 * kSP;          // column union of a pass (per-slice ranges shift)
-    constexpr int kWinStride = kWinRows + 2 * kRowPad;
+    constexpr int kWinStride = kWinRows + 2 * kRowPad + 1;   // odd: staging writes avoid bank conflicts
     static_assert(NPAIR <= 2 * kThreads, "a thread owns at most two pairs");
     __shared__ float Z[kTK * NPAIR];                // Z[k][pair]: z-profile of each (slice, column) pair
     __shared__ float xiq[NPAIR];                    // xi of the pair's column on its slice, relative to q0
     __shared__ float win[kWinCols * kWinStride];    // residual window, column-major, zero-padded rows
     __shared__ int colA[kSP], colN[kSP];            // first column and column count per slice
     __shared__ float dirS[kSP];                     // +1 if xi increases along the slice's columns, else -1
-    __shared__ int rowLo, rowHi;
 
     const int tid = threadIdx.x;
     const int tiles_x = (geo.nx + kTQ - 1) / kTQ, tiles_y = (geo.ny + kTQ - 1) / kTQ;
@@ -168,17 +167,61 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(const float *__restrict__ 
                     colA[tid] = a;
                     colN[tid] = n;
                 }
-                if (tid == 0) {
-                    rowLo = INT_MAX;
-                    rowHi = INT_MIN;
-                }
                 __syncthreads();
-                // 2a. pair geometry: xi for step 3, the ray parameter for the profile, and
-                //     the block's row range
+                // 2a. the pass's detector window: columns [c0, c1] (union of the slices'
+                //     ranges) and every row that can reach z in (k0 - 1, k0 + kTK).  The
+                //     ray parameter tau is monotone along a detector row (it is inversely
+                //     proportional to the column's D_a, which is affine in the column) and
+                //     affine in the slice index, so its extremes over the pass sit at the
+                //     corner (first/last column, first/last slice) pairs; the detector row
+                //     of a given height is monotone in tau.
+                int c0 = INT_MAX, c1 = -1;
+#pragma unroll
+                for (int m = 0; m < kSP; ++m)
+                    if (colN[m] > 0) {
+                        c0 = min(c0, colA[m]);
+                        c1 = max(c1, colA[m] + colN[m] - 1);
+                    }
+                if (c1 < 0) continue;   // uniform across the block
+                int r0, nR;
+                {
+                    const int mA = mt0 + half * kSP, mB = min(mA + kSP - 1, na - 1);
+                    const ColParam ca = cols[c0], cb = cols[c1];
+                    const double t00 = fma((double)mA, ca.t1, ca.t0), t01 = fma((double)mB, ca.t1, ca.t0);
+                    const double t10 = fma((double)mA, cb.t1, cb.t0), t11 = fma((double)mB, cb.t1, cb.t0);
+                    // bounds in FP32 (rounding is far below the one-row margins)
+                    const float imin = 1.0f / (float)(fmax(fmax(t00, t01), fmax(t10, t11)) * dvz);
+                    const float imax = 1.0f / (float)(fmin(fmin(t00, t01), fmin(t10, t11)) * dvz);
+                    const float e0 = (float)((double)(k0 - 1) - geo.cz), e1 = (float)((double)(k0 + kTK) - geo.cz);
+                    const float a = e0 * imin, b = e0 * imax, c = e1 * imin, d = e1 * imax;
+                    const float rlo = fminf(fminf(a, b), fminf(c, d)) + geo.cv;
+                    const float rhi = fmaxf(fmaxf(a, b), fmaxf(c, d)) + geo.cv;
+                    r0 = max(0, (int)floorf(rlo) - 1);
+                    nR = min(geo.nv - 1, (int)ceilf(rhi) + 1) - r0 + 1;
+                }
+                if (nR <= 0) continue;   // uniform
+                const int nC = c1 - c0 + 1;
+                const bool staged = nR <= kWinRows && nC <= kWinCols;
+                // staging: every load is issued before the LDS writes; consecutive lanes
+                // read consecutive columns (contiguous in memory); addresses are clamped
+                // into the detector and entries outside the window are written as 0
+                constexpr int kWinSize = kWinCols * kWinStride;
+                constexpr int kIt = (kWinSize + kThreads - 1) / kThreads;
+                float stv[kIt];
+                if (staged) {
+#pragma unroll
+                    for (int it = 0; it < kIt; ++it) {
+                        const int e = tid + it * kThreads;
+                        const int col = e % kWinCols, row = e / kWinCols;
+                        const int r = min(max(r0 + row - kRowPad, 0), geo.nv - 1);
+                        const int cc = min(c0 + col, geo.nu - 1);
+                        stv[it] = rwv[(int64_t)r * geo.nu + cc];
+                    }
+                }
+                // 2b. pair geometry: xi for step 3 and the ray parameter for the profile
                 double ptau[2] = {0.0, 0.0};
                 int pcol[2] = {0, 0};
                 bool pin[2] = {false, false};
-                int rlo = INT_MAX, rhi = INT_MIN;
 #pragma unroll
                 for (int sI = 0; sI < 2; ++sI) {
                     const int pr = tid + sI * kThreads;
@@ -194,56 +237,28 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(const float *__restrict__ 
                                 pin[sI] = true;
                                 pcol[sI] = c;
                                 ptau[sI] = fma(fm, cp.t1, cp.t0);
-                                const double rowz = ptau[sI] * dvz;
-                                rlo = min(rlo, (int)floor(((double)(k0 - 1) - geo.cz) / rowz + (double)geo.cv) - 1);
-                                rhi = max(rhi, (int)ceil(((double)(k0 + kTK) - geo.cz) / rowz + (double)geo.cv) + 1);
                             }
                         }
                         xiq[pr] = xl;
                     }
                 }
-                for (int off = 32; off > 0; off >>= 1) {
-                    rlo = min(rlo, __shfl_xor(rlo, off, 64));
-                    rhi = max(rhi, __shfl_xor(rhi, off, 64));
-                }
-                if ((tid & 63) == 0) {
-                    atomicMin(&rowLo, rlo);
-                    atomicMax(&rowHi, rhi);
+                if (staged) {
+#pragma unroll
+                    for (int it = 0; it < kIt; ++it) {
+                        const int e = tid + it * kThreads;
+                        if (e < kWinSize) {
+                            const int col = e % kWinCols, row = e / kWinCols;
+                            const bool inside = row >= kRowPad && row < kRowPad + nR && col < nC;
+                            win[col * kWinStride + row] = inside ? stv[it] : 0.0f;
+                        }
+                    }
                 }
                 __syncthreads();
                 if (tid < kSP) {
                     const int n = colN[tid];
                     dirS[tid] = (n >= 2 && xiq[(n - 1) * kSP + tid] < xiq[tid]) ? -1.0f : 1.0f;
                 }
-                // the staged window: rows [r0, r0 + nR), columns [c0, c0 + nC)
-                int c0 = INT_MAX, c1 = -1;
-#pragma unroll
-                for (int m = 0; m < kSP; ++m)
-                    if (colN[m] > 0) {
-                        c0 = min(c0, colA[m]);
-                        c1 = max(c1, colA[m] + colN[m] - 1);
-                    }
-                // No pair reaching the tile leaves rowLo > rowHi (INT_MAX / INT_MIN): skip
-                // before forming the row count, which would overflow.
-                if (c1 < 0 || rowLo > rowHi) continue;   // uniform across the block
-                const int r0 = max(rowLo, 0), r1 = min(rowHi, geo.nv - 1);
-                const int nR = r1 - r0 + 1, nC = c1 - c0 + 1;
-                if (nR <= 0) continue;
-                const bool staged = nR <= kWinRows && nC <= kWinCols;
-                if (staged) {
-                    const int lane = tid & 63, wv = tid >> 6;
-                    for (int col = lane; col < nC; col += 64) {
-                        float *__restrict__ wc = win + col * kWinStride;
-                        for (int row = wv; row < kWinStride; row += kThreads / 64) {
-                            // the load address is clamped into the detector; pad rows read 0
-                            const int r = min(max(r0 + row - kRowPad, 0), geo.nv - 1);
-                            const float v = rwv[(int64_t)r * geo.nu + c0 + col];
-                            wc[row] = (row >= kRowPad && row < kRowPad + nR) ? v : 0.0f;
-                        }
-                    }
-                }
-                __syncthreads();
-                // 2b. one lane per pair gathers the pair's z-profile
+                // 2c. one lane per pair gathers the pair's z-profile
 #pragma unroll
                 for (int sI = 0; sI < 2; ++sI) {
                     const int pr = tid + sI * kThreads;
@@ -344,7 +359,9 @@ static hipError_t launch_bp_w(const fbl_plan *p, const float *rw, const ViewList
                               bool accumulate, float *g, hipStream_t st)
 {
     switch (p->bp_cand) {
+    case 3: return launch_bp_t<WP, 3>(p, rw, vl, nb, first, accumulate, g, st);
     case 4: return launch_bp_t<WP, 4>(p, rw, vl, nb, first, accumulate, g, st);
+    case 5: return launch_bp_t<WP, 5>(p, rw, vl, nb, first, accumulate, g, st);
     case 6: return launch_bp_t<WP, 6>(p, rw, vl, nb, first, accumulate, g, st);
     default: return launch_bp_t<WP, 8>(p, rw, vl, nb, first, accumulate, g, st);
     }

@@ -320,11 +320,12 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
     // Backprojection: the largest number of detector columns crossing one slice of a tile
     // (kernel arithmetic replayed in FP32 over every view, class, slice and tile), which
     // sizes the tile's LDS pair table; and the number of detector rows within one voxel
-    // of a z-position, 2 / (row spacing in voxels) + 1, which sizes the profile gather.
+    // of a z-position, ceil(2 / (row spacing in voxels)), which sizes the profile gather.
     {
         const double rowz_min = tau_min * (g->dv / g->hz);
-        const double cand = std::floor(2.0 / rowz_min) + 2.0;
-        p->bp_cand = cand <= 4.0 ? 4 : cand <= 6.0 ? 6 : cand <= 8.0 ? 8 : 0;
+        // rows with eta in an open interval of length 2: at most ceil(2 / spacing)
+        const double cand = std::ceil(2.0 / rowz_min + 1e-4);
+        p->bp_cand = cand <= 3.0 ? 3 : cand <= 4.0 ? 4 : cand <= 5.0 ? 5 : cand <= 6.0 ? 6 : cand <= 8.0 ? 8 : 0;
         if (p->bp_cand == 0) {
             free_plan(p);
             return fail(FBL_E_GEOMETRY, "detector rows are too fine for the voxel size (%.3f voxels apart, min 0.34)",
