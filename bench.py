@@ -58,34 +58,39 @@ def measured_traffic(cfg: str, bytes_per_launch: float):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(g, b32, views, alpha0, beta, lo, hi):
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload: one FB-LISA
-    iteration from x = 0 on the first mini-batch."""
+def cpu_baseline(g, b32, perms, B, alpha0, beta, lo, hi, min_seconds=12.0, max_iters=4):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload: FB-LISA
+    iterations from x = 0 on the run's first mini-batches, until about min_seconds of host
+    time have passed (at most max_iters iterations)."""
     import oracle
     b64 = b32.astype(np.float64)
-    x0 = np.zeros(g.vol_shape)
-    n_fp = 0
-
+    x = np.zeros(g.vol_shape)
+    calls = {"fp": 0, "bp": 0}
+    n_iter = n_trials = 0
     t0 = time.perf_counter()
-    f0, grad, _ = oracle.objective_and_gradient(g, x0, b64, views)
-    n_fp += 1
-    calls = {"fp": 1, "bp": 1}
-
-    def fun(z):
+    while n_iter < max_iters and (n_iter == 0 or time.perf_counter() - t0 < min_seconds):
+        views = perms[n_iter][:B]
+        f0, grad, _ = oracle.objective_and_gradient(g, x, b64, views)
         calls["fp"] += 1
-        return oracle.objective(g, z, b64, views)
+        calls["bp"] += 1
 
-    alpha, xbar, fbar, trials = oracle.line_search(fun, x0, f0, grad, alpha0, beta, 0.0, lo, hi)
+        def fun(z, views=views):
+            calls["fp"] += 1
+            return oracle.objective(g, z, b64, views)
+
+        alpha, x, fbar, trials = oracle.line_search(fun, x, f0, grad, alpha0, beta, 0.0, lo, hi)
+        n_iter += 1
+        n_trials += len(trials)
     dt = time.perf_counter() - t0
-    updates = (calls["fp"] + calls["bp"]) * g.d * len(views)
+    updates = (calls["fp"] + calls["bp"]) * g.d * B
     return {
         "value": updates / dt / 1e9,
         "unit": "GUPS",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": "one FB-LISA iteration (objective, gradient, %d line-search trials) of the same workload "
-                  "from x = 0 on its first %d-view mini-batch: %d forward + %d backprojection calls in %.1f s"
-                  % (len(trials), len(views), calls["fp"], calls["bp"], dt),
+        "sample": "%d FB-LISA iterations (objective, gradient, %d line-search trials) of the same workload from "
+                  "x = 0 on its first %d-view mini-batches: %d forward + %d backprojection calls in %.1f s"
+                  % (n_iter, n_trials, B, calls["fp"], calls["bp"], dt),
     }
 
 
@@ -144,29 +149,32 @@ def main(argv=None):
         print(json.dumps({"probe": args.config, "copy_bytes": src.numel() * 4,
                           "forward_bytes_model": B * (g.d * 4 + 4 * g.n_p)}), flush=True)
         return 0
-    run = fbl.FBLisa(g, b_dev, n0=B, epochs=cfg["epochs"], alpha0=alpha0, beta=beta, lo=cfg["lo"], hi=cfg["hi"],
-                     time_calls=False)
+    run = fbl.FBLisa(g, b_dev, n0=B, epochs=cfg["epochs"], alpha0=alpha0, beta=beta, lo=cfg["lo"], hi=cfg["hi"])
     for k in range(args.warmup):
         run.iterate(perms[k][:B])
     torch.cuda.synchronize()
-    run.time_calls = True
-    run.call_events.clear()
+    run.plan.timing(True)  # HIP events around every kernel launch, on the launch stream
     n_hist = len(run.history)
     t0 = time.perf_counter()
     for k in range(args.warmup, args.warmup + args.steps):
         run.iterate(perms[k][:B])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    kt = run.plan.timing_read()
+    run.plan.timing(False)
     timed = run.history[n_hist:]
-    calls = run.call_times_ms()
-    n_fp = calls["forward"][1]
-    n_bp = calls["backproject"][1]
+    n_fp = kt["forward"][1]
+    n_bp = kt["backproject"][1]
     updates = (n_fp + n_bp) * g.d * B
     wall = t1 - t0
     gups = updates / wall / 1e9
-    t_fp = calls["forward"][0] * 1e-3
-    t_bp = calls["backproject"][0] * 1e-3
-    t_st = calls["step"][0] * 1e-3
+    kernel_us = {k: round(ms / n * 1e3, 2) for k, (ms, n) in kt.items() if n}
+    t_fp = kt["forward"][0] / n_fp * 1e-3            # fp_kernel alone
+    t_bp = kt["backproject"][0] / n_bp * 1e-3        # bp_kernel alone
+    t_fin = kt["finalize"][0] / max(1, kt["finalize"][1]) * 1e-3
+    t_fp_call = (kt["forward"][0] + kt["transpose"][0]) / n_fp * 1e-3 + t_fin   # whole forward call
+    t_bp_call = (kt["backproject"][0] + kt["prescale"][0]) / n_bp * 1e-3
+    t_st = kt["step"][0] / kt["step"][1] * 1e-3                # step_kernel alone
 
     # roofline of the dominant kernel (forward projection): the per-view block model,
     # each view reads the volume once and writes its n_p FP32 values
@@ -201,18 +209,23 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "fp_kernel (forward projection call, incl. its loss reduction)",
+            "kernel": "fp_kernel (forward projection with residual and loss partials)",
             "bytes_per_launch": bytes_fp,
         },
-        "per_call_ms": {"forward": round(t_fp * 1e3, 4), "backproject": round(t_bp * 1e3, 4),
+        "kernel_us": kernel_us,
+        "backproject_roofline": {"achieved": round(bytes_fp / t_bp / 1e9, 1), "frac": round(bytes_fp / t_bp / 1e9 /
+                                                                                          HBM_PEAK_GBS, 4)},
+        "step_hbm": {"bytes_per_launch": 12 * g.d, "achieved": round(12 * g.d / t_st / 1e9, 1),
+                     "frac": round(12 * g.d / t_st / 1e9 / HBM_PEAK_GBS, 4)},
+        "per_call_ms": {"forward": round(t_fp_call * 1e3, 4), "backproject": round(t_bp_call * 1e3, 4),
                         "step": round(t_st * 1e3, 4)},
         "gups_per_op": {"forward": round(g.d * B / t_fp / 1e9, 2), "backproject": round(g.d * B / t_bp / 1e9, 2)},
-        "calls": {"forward": n_fp, "backproject": n_bp, "step": calls["step"][1]},
+        "calls": {"forward": n_fp, "backproject": n_bp, "step": kt["step"][1]},
         "mean_backtracks": float(np.mean([it.backtracks for it in timed])),
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        rec["cpu_baseline"] = cpu_baseline(g, b32, perms[0][:B], alpha0, beta, cfg["lo"], cfg["hi"])
+        rec["cpu_baseline"] = cpu_baseline(g, b32, perms, B, alpha0, beta, cfg["lo"], cfg["hi"])
     print(json.dumps(rec), flush=True)
     return 0
 

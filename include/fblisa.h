@@ -136,6 +136,24 @@ FBL_API int fb_lisa_backproject(fbl_plan *plan, const float *r, const int32_t *v
 FBL_API int fb_lisa_step(fbl_plan *plan, const void *x, const float *g, double alpha, double mu, double lo, double hi,
                  void *xbar, double *red_dev, void *stream);
 
+/* Launch timing, for measurement.  While enabled, every kernel launch a compute call
+ * makes is bracketed by a pair of HIP events on the call's stream; fbl_timing_read waits
+ * for the recorded events, returns per kernel the summed duration (ms) and the number of
+ * launches since timing was enabled or last read, and clears the record.  Disabled by
+ * default; enabling clears any earlier record, disabling keeps it for a later read.  Event creation may allocate driver
+ * resources, so a timing plan is not for callers that cannot allocate. */
+enum {
+    FBL_K_FORWARD = 0,      /* forward projection with residual and loss partials */
+    FBL_K_TRANSPOSE = 1,    /* y-fastest copy of the volume for x = const slices */
+    FBL_K_FINALIZE = 2,     /* FP64 reduction of per-block partials */
+    FBL_K_PRESCALE = 3,     /* path-length weighting of the residual */
+    FBL_K_BACKPROJECT = 4,  /* matched backprojection */
+    FBL_K_STEP = 5,         /* prox trial with its partial inner products */
+    FBL_K_COUNT = 6
+};
+FBL_API int fbl_timing_enable(fbl_plan *plan, int on);
+FBL_API int fbl_timing_read(fbl_plan *plan, double ms[FBL_K_COUNT], int64_t launches[FBL_K_COUNT]);
+
 /* Message of the last failed call on this thread ("" if none); valid until the next
  * call on the same thread. */
 FBL_API const char *fbl_last_error(void);

@@ -24,7 +24,8 @@ _VOL_DTYPES = {"f32": (FBL_F32, torch.float32), "bf16": (FBL_BF16, torch.bfloat1
 _PROJ_DTYPES = {"f32": (FBL_F32, torch.float32), "f16": (FBL_F16, torch.float16)}
 
 EXPORTED = ("fbl_geometry_check", "fbl_plan_create", "fbl_plan_destroy", "fb_lisa_forward",
-            "fb_lisa_backproject", "fb_lisa_step", "fbl_last_error")
+            "fb_lisa_backproject", "fb_lisa_step", "fbl_timing_enable", "fbl_timing_read", "fbl_last_error")
+KERNELS = ("forward", "transpose", "finalize", "prescale", "backproject", "step")  # FBL_K_* order
 
 
 class FblError(RuntimeError):
@@ -56,10 +57,12 @@ def _load() -> ctypes.CDLL:
     lib.fb_lisa_backproject.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_double, P, P]
     lib.fb_lisa_step.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  P, P, P]
+    lib.fbl_timing_enable.argtypes = [P, ctypes.c_int]
+    lib.fbl_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.fbl_last_error.argtypes = []
     lib.fbl_last_error.restype = ctypes.c_char_p
     for name in ("fbl_geometry_check", "fbl_plan_create", "fb_lisa_forward", "fb_lisa_backproject",
-                 "fb_lisa_step"):
+                 "fb_lisa_step", "fbl_timing_enable", "fbl_timing_read"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -149,6 +152,17 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def timing(self, on: bool = True) -> None:
+        """Start (and clear) or stop per-launch event timing inside the library."""
+        _check(lib.fbl_timing_enable(self.handle, 1 if on else 0))
+
+    def timing_read(self) -> dict:
+        """{kernel: (summed ms, launches)} since timing was enabled or last read; clears the record."""
+        ms = (ctypes.c_double * len(KERNELS))()
+        n = (ctypes.c_int64 * len(KERNELS))()
+        _check(lib.fbl_timing_read(self.handle, ms, n))
+        return {k: (ms[i], int(n[i])) for i, k in enumerate(KERNELS)}
 
     def __enter__(self):
         return self

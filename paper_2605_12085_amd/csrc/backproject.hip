@@ -86,7 +86,7 @@ __device__ __forceinline__ void pair_profile(float a0, float rowz, int t_lo, int
 }
 
 template <int WP, int NC>
-__global__ __launch_bounds__(kThreads, 3) void bp_kernel(const float *__restrict__ rw, Geo geo, DeviceTables tab,
+__global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const float *__restrict__ rw, Geo geo, DeviceTables tab,
                                                       ViewList vl, int nb, int first, int accumulate,
                                                       float *__restrict__ g)
 {

@@ -7,6 +7,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/fblisa.h"
 
 namespace fbl {
@@ -86,6 +88,14 @@ struct fbl_plan {
     int fp_line;                  // per-thread LDS line length of the forward
     int bp_pairs;                 // detector columns per slice the backprojection tile holds
     int bp_cand;                  // detector rows examined per voxel in the z-profile gather
+    // launch timing (off unless fbl_timing_enable): event pairs around each launch
+    struct TimedLaunch {
+        int kernel;
+        hipEvent_t start, stop;
+    };
+    bool timing_on;
+    std::vector<TimedLaunch> timed;
+    std::vector<hipEvent_t> event_pool;
 };
 
 namespace fbl {

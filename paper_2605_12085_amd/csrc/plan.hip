@@ -161,6 +161,11 @@ void free_plan(fbl_plan *p)
     (void)hipFree(p->d_partials);
     (void)hipFree(p->d_rw);
     (void)hipFree(p->d_xt);
+    for (auto &t : p->timed) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    for (hipEvent_t ev : p->event_pool) (void)hipEventDestroy(ev);
     if (cur >= 0 && cur != p->device) (void)hipSetDevice(cur);
     delete[] p->angles_host;
     delete[] p->view_axis0;
@@ -183,6 +188,34 @@ int check_call(const fbl_plan *p, const int32_t *views, int32_t B)
     if (cur != p->device)
         return fail(FBL_E_INVALID, "the current device (%d) is not the plan's device (%d)", cur, p->device);
     return FBL_OK;
+}
+
+hipError_t pooled_event(fbl_plan *p, hipEvent_t *ev)
+{
+    if (!p->event_pool.empty()) {
+        *ev = p->event_pool.back();
+        p->event_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(ev);
+}
+
+// Enqueue one kernel through `launch`, bracketed by timing events while timing is on.
+template <typename F>
+hipError_t timed(fbl_plan *p, int kernel, hipStream_t st, F &&launch)
+{
+    if (!p->timing_on) return launch();
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = pooled_event(p, &a);
+    if (e == hipSuccess) e = pooled_event(p, &b);
+    if (e == hipSuccess) e = hipEventRecord(a, st);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, st);
+    if (e != hipSuccess) return e;
+    p->timed.push_back({kernel, a, b});
+    return hipSuccess;
 }
 
 ViewList chunk(const int32_t *views, int first, int nb)
@@ -427,16 +460,20 @@ int fb_lisa_forward(fbl_plan *p, const void *x, const int32_t *views, int32_t B,
     for (int32_t k = 0; k < B; ++k) need_xt = need_xt || p->view_axis0[views[k]];
     if (need_xt) {
         // views that march x = const slices read a y-fastest copy of x
-        hipError_t e = launch_transpose(p, x, st);
+        hipError_t e = timed(p, FBL_K_TRANSPOSE, st, [&] { return launch_transpose(p, x, st); });
         if (e != hipSuccess) return hip_fail(e, "volume transpose launch");
     }
     for (int first = 0; first < B; first += kViewsPerLaunch) {
         const int nb = B - first < kViewsPerLaunch ? B - first : kViewsPerLaunch;
-        hipError_t e = launch_forward(p, x, chunk(views, first, nb), nb, first, b, y, loss_dev != nullptr, st);
+        const ViewList vl = chunk(views, first, nb);
+        hipError_t e = timed(p, FBL_K_FORWARD, st,
+                             [&] { return launch_forward(p, x, vl, nb, first, b, y, loss_dev != nullptr, st); });
         if (e != hipSuccess) return hip_fail(e, "forward projection launch");
     }
     if (loss_dev) {
-        hipError_t e = launch_finalize_sum(p->d_partials, (int64_t)B * p->fp_blocks_per_view, 1, loss_scale, loss_dev, st);
+        const int64_t n = (int64_t)B * p->fp_blocks_per_view;
+        hipError_t e = timed(p, FBL_K_FINALIZE, st,
+                             [&] { return launch_finalize_sum(p->d_partials, n, 1, loss_scale, loss_dev, st); });
         if (e != hipSuccess) return hip_fail(e, "loss reduction launch");
     }
     return ok();
@@ -453,12 +490,16 @@ int fb_lisa_backproject(fbl_plan *p, const float *r, const int32_t *views, int32
     hipStream_t st = (hipStream_t)stream;
     for (int first = 0; first < B; first += kViewsPerLaunch) {
         const int nb = B - first < kViewsPerLaunch ? B - first : kViewsPerLaunch;
-        hipError_t e = launch_prescale(p, r, chunk(views, first, nb), nb, first, grad_scale, p->d_rw, st);
+        const ViewList vl = chunk(views, first, nb);
+        hipError_t e = timed(p, FBL_K_PRESCALE, st,
+                             [&] { return launch_prescale(p, r, vl, nb, first, grad_scale, p->d_rw, st); });
         if (e != hipSuccess) return hip_fail(e, "residual weighting launch");
     }
     for (int first = 0; first < B; first += kViewsPerLaunch) {
         const int nb = B - first < kViewsPerLaunch ? B - first : kViewsPerLaunch;
-        hipError_t e = launch_backproject(p, p->d_rw, chunk(views, first, nb), nb, first, first > 0, g, st);
+        const ViewList vl = chunk(views, first, nb);
+        hipError_t e = timed(p, FBL_K_BACKPROJECT, st,
+                             [&] { return launch_backproject(p, p->d_rw, vl, nb, first, first > 0, g, st); });
         if (e != hipSuccess) return hip_fail(e, "backprojection launch");
     }
     return ok();
@@ -482,10 +523,49 @@ int fb_lisa_step(fbl_plan *p, const void *x, const float *g, double alpha, doubl
     if (cur != p->device) return fail(FBL_E_INVALID, "the current device is not the plan's device");
     hipStream_t st = (hipStream_t)stream;
     int64_t nparts = 0;
-    e = launch_step(p, x, g, alpha, mu, lo, hi, xbar, &nparts, st);
+    e = timed(p, FBL_K_STEP, st, [&] { return launch_step(p, x, g, alpha, mu, lo, hi, xbar, &nparts, st); });
     if (e != hipSuccess) return hip_fail(e, "step launch");
-    e = launch_finalize_sum(p->d_partials, nparts, 3, 1.0, red_dev, st);
+    e = timed(p, FBL_K_FINALIZE, st, [&] { return launch_finalize_sum(p->d_partials, nparts, 3, 1.0, red_dev, st); });
     if (e != hipSuccess) return hip_fail(e, "step reduction launch");
+    return ok();
+}
+
+int fbl_timing_enable(fbl_plan *p, int on)
+{
+    if (!p) return fail(FBL_E_INVALID, "plan is NULL");
+    if (on) {
+        double ms[FBL_K_COUNT];
+        int64_t n[FBL_K_COUNT];
+        int rc = fbl_timing_read(p, ms, n);  // waits for and drops any earlier record
+        if (rc != FBL_OK) return rc;
+    }
+    p->timing_on = on != 0;
+    return ok();
+}
+
+int fbl_timing_read(fbl_plan *p, double ms[FBL_K_COUNT], int64_t launches[FBL_K_COUNT])
+{
+    if (!p || !ms || !launches) return fail(FBL_E_INVALID, "plan, ms and launches must be non-NULL");
+    for (int k = 0; k < FBL_K_COUNT; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    hipError_t first_err = hipSuccess;
+    for (auto &t : p->timed) {
+        float dt = 0.0f;
+        hipError_t e = hipEventSynchronize(t.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&dt, t.start, t.stop);
+        if (e == hipSuccess) {
+            ms[t.kernel] += dt;
+            launches[t.kernel] += 1;
+        } else if (first_err == hipSuccess) {
+            first_err = e;
+        }
+        p->event_pool.push_back(t.start);
+        p->event_pool.push_back(t.stop);
+    }
+    p->timed.clear();
+    if (first_err != hipSuccess) return hip_fail(first_err, "reading launch timing events");
     return ok();
 }
 

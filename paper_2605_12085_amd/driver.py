@@ -86,7 +86,7 @@ class FBLisa:
                  mu: float = 0.0, lo: float = 0.0, hi: float = math.inf, C: Optional[float] = None,
                  n_max: Optional[int] = None, eps: Callable[[int], float] = eps_power, j_max: int = 50,
                  x0: Optional[torch.Tensor] = None, vol_dtype: str = "f32", proj_dtype: Optional[str] = None,
-                 plan: Optional[Plan] = None, time_calls: bool = False):
+                 plan: Optional[Plan] = None):
         self.geom = geom
         self.n = int(geom.n_views)
         self.n0, self.epochs = int(n0), int(epochs)
@@ -112,28 +112,6 @@ class FBLisa:
         self.host = torch.zeros(8, dtype=torch.float64).pin_memory()
         self.k = 0
         self.history: List[Iteration] = []
-        # optional per-call HIP event pairs on the launch stream: (name, start, end)
-        self.time_calls = time_calls
-        self.call_events: List[tuple] = []
-
-    def _timed(self, name, fn, *a, **kw):
-        if not self.time_calls:
-            return fn(*a, **kw)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        out = fn(*a, **kw)
-        e1.record()
-        self.call_events.append((name, e0, e1))
-        return out
-
-    def call_times_ms(self):
-        """Mean and count of the recorded call durations per call kind (synchronises)."""
-        torch.cuda.synchronize()
-        acc = {}
-        for name, e0, e1 in self.call_events:
-            acc.setdefault(name, []).append(e0.elapsed_time(e1))
-        return {k: (float(np.mean(v)), len(v)) for k, v in acc.items()}
 
     # -- one iteration (Steps 2b-2d) ---------------------------------------------------
     def iterate(self, views: Sequence[int], alpha_init: Optional[float] = None, epoch: int = 0,
@@ -144,15 +122,14 @@ class FBLisa:
         f_scale = self.n / (2.0 * B)
         r, rbar = self.r[:B], self.rbar[:B]
         plan = self.plan
-        self._timed("forward", fb_lisa_forward, plan, self.x, v, self.b, r, self.scal[0:1], f_scale)
-        self._timed("backproject", fb_lisa_backproject, plan, r, v, self.n / float(B), self.g)
+        fb_lisa_forward(plan, self.x, v, self.b, r, self.scal[0:1], f_scale)
+        fb_lisa_backproject(plan, r, v, self.n / float(B), self.g)
         alpha = self.alpha0 if alpha_init is None else float(alpha_init)
         trials: List[Trial] = []
         stream = torch.cuda.current_stream()
         for j in range(self.j_max + 1):
-            self._timed("step", fb_lisa_step, plan, self.x, self.g, alpha, self.mu, self.lo, self.hi, self.xbar,
-                        self.scal[4:7])
-            self._timed("forward", fb_lisa_forward, plan, self.xbar, v, self.b, rbar, self.scal[2:3], f_scale)
+            fb_lisa_step(plan, self.x, self.g, alpha, self.mu, self.lo, self.hi, self.xbar, self.scal[4:7])
+            fb_lisa_forward(plan, self.xbar, v, self.b, rbar, self.scal[2:3], f_scale)
             self.host.copy_(self.scal, non_blocking=True)
             stream.synchronize()
             h = self.host.tolist()

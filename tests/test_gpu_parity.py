@@ -235,6 +235,29 @@ def test_host_checks_launch_nothing(fbl):
     assert e.value.code == 3
 
 
+def test_launch_timing_records_every_kernel(fbl):
+    import torch
+    g = syn.tiny_geometry(n=8, det=12, views=16)
+    x = _t(syn.random_volume(g, seed=3).astype(np.float32))
+    b = torch.zeros((g.n_views, g.nv, g.nu), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with fbl.Plan(g) as plan:
+        views = list(range(g.n_views))   # includes views that march x = const slices
+        plan.timing(True)
+        r = fbl.fb_lisa_forward(plan, x, views, b, loss=loss)
+        gr = fbl.fb_lisa_backproject(plan, r, views)
+        fbl.fb_lisa_step(plan, x, gr, 1e-3)
+        kt = plan.timing_read()
+        assert {k: n for k, (_, n) in kt.items()} == {"forward": 1, "transpose": 1, "finalize": 2, "prescale": 1,
+                                                       "backproject": 1, "step": 1}
+        assert all(ms > 0 for ms, n in kt.values())
+        assert all(n == 0 for _, n in plan.timing_read().values())   # read clears
+        plan.timing(False)
+        fbl.fb_lisa_forward(plan, x, views)
+        assert all(n == 0 for _, n in plan.timing_read().values())
+        torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("cfg", ["c2"])
 def test_full_size_sampled_parity(fbl, orc, cfg):
     # Full-size geometry and the batch size the benchmark times; rays and voxels are
