@@ -98,7 +98,9 @@ FBL_API int fbl_geometry_check(const fbl_geometry *g);
  * per-column ray parameters in FP64 on the host, and allocates the plan's device tables,
  * its reduction workspace and a [max_batch][nv][nu] FP32 scratch used by the
  * backprojection.  max_batch in [1, n_views].  vol_dtype is FBL_F32, FBL_BF16 or
- * FBL_F16 (x and xbar); proj_dtype is FBL_F32 or FBL_F16 (b).  On failure *out is NULL.
+ * FBL_F16 (x and xbar); proj_dtype is FBL_F32, FBL_BF16 or FBL_F16 (b).  Storage types
+ * only change what is read and written: every ray sum and the residual are formed in
+ * FP32 and every reduction in FP64.  On failure *out is NULL.
  * The plan is released with fbl_plan_destroy (NULL is accepted). */
 FBL_API int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype, int32_t max_batch,
                     fbl_plan **out);

@@ -254,17 +254,56 @@ def prox(v, alpha: float, mu: float, lo: float = 0.0, hi: float = math.inf) -> n
     return np.minimum(np.maximum(_f64(v) - alpha * mu, lo), hi)
 
 
+# ----------------------------------------------------------------------------------
+# storage rounding (the precision form stores x in 16-bit types, computes in FP32/FP64)
+# ----------------------------------------------------------------------------------
+
+def round_bf16(v) -> np.ndarray:
+    """Round FP64 values once to bfloat16 (8 significant bits, FP32 exponent range),
+    to nearest with ties to even, returned as FP64.
+
+    From the definition: a finite v with |v| in [2^(e-1), 2^e) has the quantum
+    2^(e-8); below the smallest normal 2^-126 the quantum stays 2^-133 (gradual
+    underflow).  v / quantum is exact (a power-of-two scaling), np.rint rounds it half
+    to even.  Results beyond the largest finite bfloat16 become infinities."""
+    v = _f64(v)
+    out = v.copy()
+    fin = np.isfinite(v) & (v != 0)
+    _, e = np.frexp(v[fin])
+    q = np.ldexp(1.0, np.maximum(e, -125) - 8)
+    r = np.rint(v[fin] / q) * q
+    big = np.ldexp(1.0, 128)
+    r = np.where(np.abs(r) >= big, np.copysign(np.inf, r), r)
+    out[fin] = r
+    return out
+
+
+def round_storage(v, storage) -> np.ndarray:
+    """Round FP64 values once to a storage type: "f32", "f16" (numpy's IEEE conversions,
+    nearest-even from FP64), "bf16" (round_bf16), or None/"f64" (unchanged)."""
+    if storage is None or storage == "f64":
+        return _f64(v)
+    if storage in ("f32", np.float32):
+        return _f64(v).astype(np.float32).astype(np.float64)
+    if storage in ("f16", np.float16):
+        with np.errstate(over="ignore"):
+            return _f64(v).astype(np.float16).astype(np.float64)
+    if storage == "bf16":
+        return round_bf16(v)
+    raise ValueError("unknown storage %r" % (storage,))
+
+
 def prox_step(x, grad, alpha: float, mu: float, lo: float = 0.0, hi: float = math.inf, storage=None):
     """Trial point of Algorithm 1 Step 2c and the inner products of (2.3).
 
-    xbar = prox(x - alpha grad); with ``storage`` (a numpy dtype such as float32) the
-    trial point is rounded to that storage type, as a stored iterate would be, before
-    d = xbar - x is formed.  Returns (xbar, <grad, d>, ||d||^2, ||grad||^2).
+    xbar = prox(x - alpha grad); with ``storage`` ("f32", "bf16", "f16" or a numpy
+    dtype) the trial point is rounded to that storage type, as a stored iterate would
+    be, before d = xbar - x is formed.  Returns (xbar, <grad, d>, ||d||^2, ||grad||^2).
     """
     x64, g64 = _f64(x), _f64(grad)
     xbar = prox(x64 - alpha * g64, alpha, mu, lo, hi)
     if storage is not None:
-        xbar = xbar.astype(storage).astype(np.float64)
+        xbar = round_storage(xbar, storage)
     d = xbar - x64
     return xbar, float(np.dot(g64.ravel(), d.ravel())), float(np.dot(d.ravel(), d.ravel())), \
         float(np.dot(g64.ravel(), g64.ravel()))
@@ -294,18 +333,21 @@ def sufficient_decrease(f_bar: float, f0: float, inner: float, sq: float, alpha:
 
 def line_search(fun: Callable[[np.ndarray], float], x: np.ndarray, f0: float, grad: np.ndarray,
                 alpha_init: float, beta: float, mu: float, lo: float, hi: float, j_max: int = 50,
-                decide: Optional[Callable[[int], bool]] = None):
+                decide: Optional[Callable[[int], bool]] = None, storage=None):
     """Backtracking of Algorithm 1, Step 2c.
 
     Starting from alpha_init, forms xbar = prox(x - alpha grad) and accepts the first
     alpha for which (2.3) holds; otherwise alpha <- beta * alpha.  ``decide`` (replay
-    mode) overrides the accept/reject decision of trial j.
+    mode) overrides the accept/reject decision of trial j.  ``storage`` rounds each
+    trial point to a storage type (see round_storage) before it is used.
     Returns (alpha, xbar, f_bar, trials).
     """
     alpha = alpha_init
     trials: List[TrialRecord] = []
     for j in range(j_max + 1):
         xbar = prox(x - alpha * grad, alpha, mu, lo, hi)
+        if storage is not None:
+            xbar = round_storage(xbar, storage)
         dlt = xbar - x
         inner = float(np.dot(grad.ravel(), dlt.ravel()))
         sq = float(np.dot(dlt.ravel(), dlt.ravel()))
@@ -378,12 +420,13 @@ def fblisa(g, b_full, *, epochs: int, n0: int, alpha0: float = 1e-3, beta: float
            x0: Optional[np.ndarray] = None, perms: Optional[np.ndarray] = None,
            j_max: int = 50, decisions: Optional[Sequence[Sequence[bool]]] = None,
            alpha_init: Optional[Callable[[int], float]] = None,
-           max_iters: Optional[int] = None, callback=None):
+           max_iters: Optional[int] = None, callback=None, storage=None):
     """Algorithm 1 (FB-LISA) in FP64 with n = n_theta (one f_i per projection angle).
 
     perms[k] is a permutation of the views for iteration k; the mini-batch is its
     first N_t entries.  ``decisions`` (replay) forces the accept/reject outcome of
     each trial.  ``alpha_init(k)`` replaces alpha_0 as the first trial step.
+    ``storage`` keeps the iterates rounded to a storage type (the arithmetic stays FP64).
     Returns (x, records).
     """
     n = g.n_views
@@ -407,7 +450,8 @@ def fblisa(g, b_full, *, epochs: int, n0: int, alpha0: float = 1e-3, beta: float
                 dk = decisions[k]
                 dec = lambda j, dk=dk: dk[j]
             alpha, xbar, f_bar, trials = line_search(
-                lambda z: objective(g, z, b_full, views), x, f0, grad, a0, beta, mu, lo, hi, j_max, dec)
+                lambda z: objective(g, z, b_full, views), x, f0, grad, a0, beta, mu, lo, hi, j_max, dec,
+                storage)
             records.append(IterRecord(t, k, np.asarray(views).copy(), f0, alpha, len(trials) - 1, trials))
             x = xbar
             if callback is not None:

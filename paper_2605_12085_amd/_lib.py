@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libfblisa.so")
 FBL_OK, FBL_E_INVALID, FBL_E_GEOMETRY, FBL_E_RANGE, FBL_E_DTYPE, FBL_E_HIP, FBL_E_NOMEM = range(7)
 FBL_F32, FBL_BF16, FBL_F16 = 0, 1, 2
 _VOL_DTYPES = {"f32": (FBL_F32, torch.float32), "bf16": (FBL_BF16, torch.bfloat16), "f16": (FBL_F16, torch.float16)}
-_PROJ_DTYPES = {"f32": (FBL_F32, torch.float32), "f16": (FBL_F16, torch.float16)}
+_PROJ_DTYPES = {"f32": (FBL_F32, torch.float32), "bf16": (FBL_BF16, torch.bfloat16), "f16": (FBL_F16, torch.float16)}
 
 EXPORTED = ("fbl_geometry_check", "fbl_plan_create", "fbl_plan_destroy", "fb_lisa_forward",
             "fb_lisa_backproject", "fb_lisa_step", "fbl_timing_enable", "fbl_timing_read", "fbl_last_error")

@@ -305,20 +305,24 @@ static hipError_t launch_fp_t(const fbl_plan *p, const void *x, const ViewList &
     }
 }
 
+template <typename TV>
+static hipError_t launch_fp_b(const fbl_plan *p, const void *x, const ViewList &vl, int nb, int first,
+                              const void *b, float *y, bool want_loss, hipStream_t st)
+{
+    switch (p->proj_dtype) {
+    case FBL_F32: return launch_fp_t<TV, float>(p, x, vl, nb, first, b, y, want_loss, st);
+    case FBL_BF16: return launch_fp_t<TV, __hip_bfloat16>(p, x, vl, nb, first, b, y, want_loss, st);
+    default: return launch_fp_t<TV, __half>(p, x, vl, nb, first, b, y, want_loss, st);
+    }
+}
+
 hipError_t launch_forward(const fbl_plan *p, const void *x, const ViewList &vl, int nb, int first, const void *b,
                           float *y, bool want_loss, hipStream_t st)
 {
-    const bool bh = p->proj_dtype == FBL_F16;
     switch (p->vol_dtype) {
-    case FBL_F32:
-        return bh ? launch_fp_t<float, __half>(p, x, vl, nb, first, b, y, want_loss, st)
-                  : launch_fp_t<float, float>(p, x, vl, nb, first, b, y, want_loss, st);
-    case FBL_BF16:
-        return bh ? launch_fp_t<__hip_bfloat16, __half>(p, x, vl, nb, first, b, y, want_loss, st)
-                  : launch_fp_t<__hip_bfloat16, float>(p, x, vl, nb, first, b, y, want_loss, st);
-    default:
-        return bh ? launch_fp_t<__half, __half>(p, x, vl, nb, first, b, y, want_loss, st)
-                  : launch_fp_t<__half, float>(p, x, vl, nb, first, b, y, want_loss, st);
+    case FBL_F32: return launch_fp_b<float>(p, x, vl, nb, first, b, y, want_loss, st);
+    case FBL_BF16: return launch_fp_b<__hip_bfloat16>(p, x, vl, nb, first, b, y, want_loss, st);
+    default: return launch_fp_b<__half>(p, x, vl, nb, first, b, y, want_loss, st);
     }
 }
 

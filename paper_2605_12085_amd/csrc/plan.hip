@@ -246,8 +246,8 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
     if (rc != FBL_OK) return rc;
     if (vol_dtype != FBL_F32 && vol_dtype != FBL_BF16 && vol_dtype != FBL_F16)
         return fail(FBL_E_DTYPE, "vol_dtype %d is not FBL_F32, FBL_BF16 or FBL_F16", (int)vol_dtype);
-    if (proj_dtype != FBL_F32 && proj_dtype != FBL_F16)
-        return fail(FBL_E_DTYPE, "proj_dtype %d is not FBL_F32 or FBL_F16", (int)proj_dtype);
+    if (proj_dtype != FBL_F32 && proj_dtype != FBL_BF16 && proj_dtype != FBL_F16)
+        return fail(FBL_E_DTYPE, "proj_dtype %d is not FBL_F32, FBL_BF16 or FBL_F16", (int)proj_dtype);
     if (max_batch < 1 || max_batch > g->n_views)
         return fail(FBL_E_RANGE, "max_batch %d outside [1, n_views=%lld]", (int)max_batch, (long long)g->n_views);
 

@@ -96,7 +96,7 @@ class FBLisa:
         self.C = constant_batch_C(self.n, self.n0, self.epochs, eps) if C is None else float(C)
         self.j_max = int(j_max)
         if proj_dtype is None:
-            proj_dtype = "f16" if b.dtype == torch.float16 else "f32"
+            proj_dtype = {torch.float16: "f16", torch.bfloat16: "bf16"}.get(b.dtype, "f32")
         self.plan = plan if plan is not None else Plan(geom, vol_dtype, proj_dtype, max_batch=self.n_max)
         dev = b.device
         self.b = b

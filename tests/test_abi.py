@@ -91,7 +91,7 @@ def test_dtype_and_batch_rejections_before_device_work():
     gh = _lib._GeomHolder(syn.tiny_geometry())
     out = ctypes.c_void_p()
     assert _lib.lib.fbl_plan_create(ctypes.byref(gh.s), 7, 0, 4, ctypes.byref(out)) == _lib.FBL_E_DTYPE
-    assert _lib.lib.fbl_plan_create(ctypes.byref(gh.s), 0, 1, 4, ctypes.byref(out)) == _lib.FBL_E_DTYPE
+    assert _lib.lib.fbl_plan_create(ctypes.byref(gh.s), 0, 3, 4, ctypes.byref(out)) == _lib.FBL_E_DTYPE
     assert _lib.lib.fbl_plan_create(ctypes.byref(gh.s), 0, 0, 0, ctypes.byref(out)) == _lib.FBL_E_RANGE
     assert _lib.lib.fbl_plan_create(ctypes.byref(gh.s), 0, 0, 17, ctypes.byref(out)) == _lib.FBL_E_RANGE
 

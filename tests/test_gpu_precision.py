@@ -1,0 +1,197 @@
+"""Precision form: volume and data stored in BF16 or FP16, ray sums in FP32, the loss and
+the line-search inner products in FP64 (HIP kernels through the C ABI).
+
+Parity with the oracle is taken on the stored values: the oracle receives exactly the
+16-bit numbers the GPU reads (rounded by its own round_storage), so the 1e-5 bar of the
+FP32 path applies unchanged.  The error of storage itself is stated against FP64:
+for a nonnegative volume every ray weight is nonnegative, so rounding each voxel with
+relative error <= u gives a ray-sum error <= u * (ray sum); the bound per view is the
+unit roundoff u (2^-8 BF16, 2^-11 FP16) plus the FP32 arithmetic.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+U = {"f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+@pytest.fixture(scope="module")
+def fbl():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2605_12085_amd as fbl
+    return fbl
+
+
+def _torch_dtype(st):
+    import torch
+    return {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[st]
+
+
+def _dev(a64, st):
+    """Device tensor holding exactly the FP64 values a64 (already representable in st)."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a64.astype(np.float32))).to(_torch_dtype(st))
+    assert np.array_equal(t.to(torch.float64).numpy(), a64)
+    return t.cuda()
+
+
+ODD = syn.Geometry(29, 41, 37, 0.9, 1.1, 1.0, 50, 33, 1.7, 1.9, 400.0, 900.0, 12,
+                   angles=[0.0, np.pi / 4, np.pi / 2, np.pi, 3 * np.pi / 2, 0.3, 1.7, 2.9, 4.0, 5.5, 0.05, 6.2])
+
+
+def _rel_views(got, ref):
+    out = []
+    for b in range(ref.shape[0]):
+        out.append(np.linalg.norm(got[b] - ref[b]) / np.linalg.norm(ref[b]))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("vol,proj", [("bf16", "f32"), ("f16", "f32"), ("f32", "f16"), ("f32", "bf16"),
+                                      ("bf16", "bf16"), ("f16", "f16")])
+def test_forward_parity_on_stored_values(fbl, orc, vol, proj):
+    import torch
+    g = ODD
+    rng = np.random.default_rng(21)
+    xs = orc.round_storage(rng.uniform(0, 0.03, g.vol_shape), vol)
+    views = np.arange(g.n_views, dtype=np.int32)
+    y64 = orc.forward(g, xs, views)
+    bs = orc.round_storage(0.5 * y64 * rng.uniform(0.5, 1.5, y64.shape), proj)
+    r_ref = y64 - bs
+    f_ref = g.n_views / (2.0 * len(views)) * float(np.sum(r_ref ** 2))
+    with fbl.Plan(g, vol_dtype=vol, proj_dtype=proj) as plan:
+        x = _dev(xs, vol)
+        b = _dev(bs, proj)
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        y = fbl.fb_lisa_forward(plan, x, views).cpu().numpy().astype(np.float64)
+        r = fbl.fb_lisa_forward(plan, x, views, b, loss=loss).cpu().numpy().astype(np.float64)
+        f = float(loss)
+    for got, ref, what in ((y, y64, "forward"), (r, r_ref, "residual")):
+        rel = _rel_views(got, ref)
+        mx = np.array([np.abs(got[k] - ref[k]).max() / np.abs(ref[k]).max() for k in range(len(views))])
+        assert rel.max() <= TOL and mx.max() <= TOL, (what, vol, proj, rel.max(), mx.max())
+    assert f == pytest.approx(f_ref, rel=TOL)
+
+
+def _storage_ulp(v, st):
+    m, e = np.frexp(np.abs(v))
+    p = {"f32": 24, "bf16": 8, "f16": 11}[st]
+    emin = {"f32": -125, "bf16": -125, "f16": -13}[st]
+    return np.ldexp(1.0, np.maximum(e, emin) - p)
+
+
+@pytest.mark.parametrize("st", ["bf16", "f16"])
+def test_step_16bit_rounds_once_like_the_oracle(fbl, orc, st):
+    import torch
+    g = ODD
+    rng = np.random.default_rng(22)
+    xs = orc.round_storage(rng.uniform(0, 0.03, g.vol_shape), st)
+    xs[rng.random(g.vol_shape) < 0.2] = 0.0
+    grad = (rng.standard_normal(g.vol_shape) * 3.0).astype(np.float32)
+    with fbl.Plan(g, vol_dtype=st) as plan:
+        for alpha, mu, lo, hi in ((1e-3, 0.0, 0.0, math.inf), (2.5e-3, 0.7, 0.0, 0.03), (1e-4, 2.0, 0.001, 0.025)):
+            red = torch.zeros(3, dtype=torch.float64, device="cuda")
+            xb, red = fbl.fb_lisa_step(plan, _dev(xs, st), torch.from_numpy(grad).cuda(), alpha, mu, lo, hi,
+                                       red=red)
+            xb = xb.to(torch.float64).cpu().numpy()
+            red = red.cpu().numpy()
+            xr, inner, sq, gg = orc.prox_step(xs, grad, alpha, mu, lo, hi, storage=st)
+            assert np.all(np.abs(xb - xr) <= _storage_ulp(xr, st))
+            assert np.mean(xb == xr) > 0.999
+            assert red[0] == pytest.approx(inner, rel=1e-9)
+            assert red[1] == pytest.approx(sq, rel=1e-9)
+            assert red[2] == pytest.approx(gg, rel=1e-12)
+
+
+def test_precision_report_512_sampled_rays(fbl, orc, capsys):
+    """Per-view relative error against the FP64 oracle on the FP64 phantom, on 1% of the
+    rays of every view, for FP32, BF16 and FP16 volume storage: 512^3 volume, 720 views,
+    768x768 detector, batches of 40 views.  Storage rounding is counted."""
+    import torch
+    name = "c3"
+    g = syn.config_geometry(name)
+    cfg = syn.CONFIGS[name]
+    _, x64 = syn.phantom(g, cfg["k"], seed=3000, hi=cfg["hi"], sub=2)
+    rng = np.random.default_rng(3002)
+    n_s = g.n_p // 100
+    pix = np.stack([np.sort(rng.choice(g.n_p, n_s, replace=False)) for _ in range(g.n_views)])
+    rays = np.stack([np.repeat(np.arange(g.n_views), n_s), (pix // g.nu).ravel(), (pix % g.nu).ravel()], axis=1)
+    ref = orc.forward_rays(g, x64, rays).reshape(g.n_views, n_s)
+    B = cfg["batch"]
+    report = {}
+    for st in ("f32", "bf16", "f16"):
+        xs = torch.from_numpy(x64.astype(np.float32)).to(_torch_dtype(st)).cuda()
+        got = np.empty((g.n_views, n_s))
+        with fbl.Plan(g, vol_dtype=st, max_batch=B) as plan:
+            for v0 in range(0, g.n_views, B):
+                vs = np.arange(v0, v0 + B, dtype=np.int32)
+                y = fbl.fb_lisa_forward(plan, xs, vs).view(B, -1)
+                idx = torch.from_numpy(pix[v0:v0 + B]).cuda()
+                got[v0:v0 + B] = torch.gather(y, 1, idx).cpu().numpy()
+        del xs
+        torch.cuda.empty_cache()
+        rel = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        report[st] = rel
+    with capsys.disabled():
+        print("\nper-view relative error vs FP64 (512^3, 720 views, 1%% of rays = %d per view):" % n_s)
+        for st, rel in report.items():
+            print("  %-4s storage: median %.3e  p99 %.3e  max %.3e  (unit roundoff %.3e)"
+                  % (st, np.median(rel), np.percentile(rel, 99), rel.max(), U[st]), flush=True)
+    assert report["f32"].max() <= TOL
+    assert report["f16"].max() <= U["f16"] + TOL
+    assert report["bf16"].max() <= U["bf16"] + TOL
+    assert np.median(report["bf16"]) > np.median(report["f16"]) > np.median(report["f32"])
+
+
+def _loop_problem(n=32, det=48, views=24, seed=300, k=6):
+    h = 64.0 / n
+    du = 96.0 / det
+    g = syn.Geometry(n, n, n, h, h, h, det, det, du, du, 500.0, 1000.0, views)
+    ells, xt = syn.phantom(g, k, seed=seed)
+    clean = syn.ellipsoid_line_integrals(g, ells, np.arange(views))
+    b = syn.add_noise(clean, 0.01, seed=seed + 1).astype(np.float32)
+    perms = syn.view_permutations(views, 200, seed=seed + 2)
+    return g, xt, b, perms
+
+
+@pytest.mark.parametrize("st", ["bf16", "f16"])
+def test_16bit_iterates_replay_and_error_against_fp64(fbl, orc, st, capsys):
+    """FB-LISA with the iterates stored in 16 bits.  Replay: the GPU follows the decisions
+    of the oracle's run with the same storage; its iterates stay within one unit roundoff
+    (relative l2) of the oracle's (they differ only where the FP32 gradient moves a value
+    across a rounding boundary).  The storage error of the reconstruction is stated
+    against the FP64 run and bounded by a few unit roundoffs."""
+    import torch
+    g, xt, b32, perms = _loop_problem()
+    epochs, n0 = 2, 4
+    b64 = b32.astype(np.float64)
+    x64, _ = orc.fblisa(g, b64, epochs=epochs, n0=n0, perms=perms)
+    xs_o = []
+    xo, rec = orc.fblisa(g, b64, epochs=epochs, n0=n0, perms=perms, storage=st,
+                         callback=lambda k, x, r: xs_o.append(x.copy()))
+    assert all(np.array_equal(orc.round_storage(x, st), x) for x in xs_o)
+    decisions = [[t.accepted for t in r.trials] for r in rec]
+    bd = torch.from_numpy(b32).cuda()
+    xs_g = []
+    run = fbl.FBLisa(g, bd, n0=n0, epochs=epochs, vol_dtype=st)
+    run.run(perms, decisions=decisions,
+            callback=lambda s, it: xs_g.append(s.x.to(torch.float64).cpu().numpy()))
+    assert len(xs_g) == len(xs_o)
+    for k, (a, b) in enumerate(zip(xs_g, xs_o)):
+        assert np.linalg.norm(a - b) <= U[st] * np.linalg.norm(b), k
+    free = fbl.FBLisa(g, bd, n0=n0, epochs=epochs, vol_dtype=st)
+    xf = free.run(perms).to(torch.float64).cpu().numpy()
+    f32 = fbl.FBLisa(g, bd, n0=n0, epochs=epochs)
+    x32 = f32.run(perms).cpu().numpy().astype(np.float64)
+    re_st, re_32 = orc.relative_error(xf, x64), orc.relative_error(x32, x64)
+    with capsys.disabled():
+        print("\n%s iterates: RE vs FP64 run %.3e (FP32 run %.3e); RMSE vs phantom %.4e (FP32 %.4e, FP64 %.4e)"
+              % (st, re_st, re_32, orc.rmse(xf, xt), orc.rmse(x32, xt), orc.rmse(x64, xt)), flush=True)
+    assert re_32 <= 1e-3
+    assert re_st <= 4 * U[st]

@@ -1,0 +1,80 @@
+"""Pins of the oracle's storage rounding (precision form: x stored in BF16/FP16).
+
+round_bf16 is written from the definition of the format (8 significant bits, FP32
+exponent range, nearest-even); it is pinned by hand-computed ties, by torch's own
+bfloat16 conversion on inputs that are exact in FP32 (where that conversion is a single
+rounding), by the half-ulp error bound and by idempotence.  FP16 uses numpy's IEEE
+conversion; hand cases pin the storage dispatch.
+"""
+import math
+
+import numpy as np
+import pytest
+
+
+def test_bf16_hand_ties(orc):
+    one = 1.0
+    cases = [
+        (one + 2.0 ** -8, one),                          # tie between 1 and 1+2^-7: even (1)
+        (one + 3 * 2.0 ** -8, one + 2.0 ** -6),          # tie between 1+2^-7 and 1+2^-6: even
+        (-(one + 2.0 ** -8), -one),
+        (one + 2.0 ** -8 + 2.0 ** -40, one + 2.0 ** -7),  # just above a tie (lost if FP32 came first)
+        (one + 2.0 ** -8 - 2.0 ** -40, one),
+        (255.0 + 0.5, 256.0),                            # 255.5: quantum 1 at [128, 256) -> tie -> 256
+        (3.0 * 2.0 ** -130, 3.0 * 2.0 ** -130),          # below 2^-126: quantum 2^-133, exact
+        (2.0 ** -134, 0.0),                              # half the smallest subnormal: tie to even 0
+        (3.0 * 2.0 ** -134, 2.0 ** -132),                # 1.5 quanta: tie to even (2 quanta)
+        (3.39e38, float(np.ldexp(1.0, 128) - np.ldexp(1.0, 120))),   # largest finite bfloat16
+        (3.4e38, math.inf),                              # beyond max + half a quantum
+        (0.0, 0.0),
+    ]
+    got = orc.round_bf16(np.array([c[0] for c in cases]))
+    for (v, want), r in zip(cases, got):
+        assert r == want, (v, r, want)
+    assert np.isinf(orc.round_bf16(np.array([2.0 ** 128 * (1 - 2.0 ** -9)]))[0])  # rounds past the max
+    assert math.copysign(1.0, orc.round_bf16(np.array([-0.0]))[0]) == -1.0
+
+
+def test_bf16_matches_torch_on_fp32_inputs(orc):
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(0)
+    x = (rng.standard_normal(200000) * 10.0 ** rng.integers(-30, 30, 200000)).astype(np.float32)
+    x = np.concatenate([x, rng.uniform(0, 0.03, 100000).astype(np.float32)])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(orc.round_bf16(x.astype(np.float64)), ref)
+
+
+def test_bf16_error_bound_and_idempotence(orc):
+    rng = np.random.default_rng(1)
+    v = rng.uniform(-1, 1, 100000) * 10.0 ** rng.uniform(-20, 20, 100000)
+    r = orc.round_bf16(v)
+    assert np.all(np.abs(r - v) <= 2.0 ** -8 * np.abs(v) * (1 + 1e-15))   # unit roundoff 2^-p, p = 8
+    assert np.array_equal(orc.round_bf16(r), r)
+    # monotone
+    s = np.sort(v)
+    assert np.all(np.diff(orc.round_bf16(s)) >= 0)
+
+
+def test_storage_dispatch(orc):
+    v = np.array([2049.0, 2051.0, 1.0 + 2.0 ** -11, 65520.0, 0.1])
+    f16 = orc.round_storage(v, "f16")
+    assert list(f16[:3]) == [2048.0, 2052.0, 1.0]
+    assert np.isinf(f16[3])
+    assert orc.round_storage(v, "f32")[4] == float(np.float32(0.1))
+    assert orc.round_storage(v, "bf16")[4] == 0.10009765625
+    assert np.array_equal(orc.round_storage(v, None), v)
+
+
+def test_prox_step_with_storage(orc):
+    rng = np.random.default_rng(2)
+    x = orc.round_bf16(rng.uniform(0, 0.03, 5000))
+    grad = rng.standard_normal(5000)
+    for st in ("bf16", "f16"):
+        xb, inner, sq, gg = orc.prox_step(x, grad, 1e-3, 0.5, 0.0, 0.03, storage=st)
+        assert np.array_equal(orc.round_storage(xb, st), xb)
+        d = xb - x
+        assert inner == pytest.approx(float(grad @ d), rel=1e-13)
+        assert sq == pytest.approx(float(d @ d), rel=1e-13)
+        exact = np.clip(x - 1e-3 * grad - 1e-3 * 0.5, 0.0, 0.03)
+        ulp = 2.0 ** -8 if st == "bf16" else 2.0 ** -11   # unit roundoff
+        assert np.all(np.abs(xb - exact) <= ulp * np.abs(exact) + 2.0 ** -24)
