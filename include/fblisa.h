@@ -41,6 +41,7 @@
 #ifndef FBLISA_H
 #define FBLISA_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #if defined(__GNUC__)
@@ -137,6 +138,37 @@ FBL_API int fb_lisa_backproject(fbl_plan *plan, const float *r, const int32_t *v
  *             order (deterministic). */
 FBL_API int fb_lisa_step(fbl_plan *plan, const void *x, const float *g, double alpha, double mu, double lo, double hi,
                  void *xbar, double *red_dev, void *stream);
+
+/* Learned initial step of the line search (Alg. 1 Step 2c starts from a proposed step;
+ * the backtracking on (2.3) still accepts or rejects every proposal).  The proposer is a
+ * perceptron with FBL_MLP_IN inputs, two ReLU hidden layers of FBL_MLP_HIDDEN units and one
+ * linear output, FP32.  Its parameters are one device FP32 vector of FBL_MLP_NPARAMS
+ * values in the order W1[64][5], b1[64], W2[64][64], b2[64], w3[64], b3 (row-major,
+ * y = w3 . relu(W2 relu(W1 x + b1) + b2) + b3).  These calls need no plan; they are
+ * stream-ordered and never synchronise.  Device arrays are 16-byte aligned. */
+enum { FBL_MLP_IN = 5, FBL_MLP_HIDDEN = 64, FBL_MLP_NPARAMS = 64 * 5 + 64 + 64 * 64 + 64 + 64 + 1 };
+
+/* Bytes of the caller-owned device workspace fbl_mlp_loss_grad needs for n samples. */
+FBL_API size_t fbl_mlp_workspace_bytes(int64_t n);
+
+/* out[i] = MLP(X[i]) for X device FP32 [n][FBL_MLP_IN], out device FP32 [n]; n >= 1. */
+FBL_API int fbl_mlp_forward(const float *params, const float *X, int64_t n, float *out, void *stream);
+
+/* Mean-squared training loss L = 1/(2n) sum_i (MLP(X[i]) - t[i])^2 and its gradient.
+ *   t         device FP32 [n] targets
+ *   grad      device FP32 [FBL_MLP_NPARAMS], overwritten with dL/dparams (FP64 sums over
+ *             samples in a fixed order, rounded once)
+ *   loss_dev  device double, or NULL: overwritten with 2 n L = sum_i e_i^2 (FP64)
+ *   work      device, fbl_mlp_workspace_bytes(n) bytes, 256-byte aligned */
+FBL_API int fbl_mlp_loss_grad(const float *params, const float *X, const float *t, int64_t n, float *grad,
+                              double *loss_dev, void *work, void *stream);
+
+/* One Adam step (Kingma and Ba) in FP32 on every parameter: m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, params -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).
+ * step >= 1 counts the updates made so far including this one; m, v device FP32 state of
+ * FBL_MLP_NPARAMS values (zero before the first step). */
+FBL_API int fbl_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step, double lr, double beta1,
+                         double beta2, double eps, void *stream);
 
 /* Launch timing, for measurement.  While enabled, every kernel launch a compute call
  * makes is bracketed by a pair of HIP events on the call's stream; fbl_timing_read waits

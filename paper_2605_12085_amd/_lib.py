@@ -24,7 +24,10 @@ _VOL_DTYPES = {"f32": (FBL_F32, torch.float32), "bf16": (FBL_BF16, torch.bfloat1
 _PROJ_DTYPES = {"f32": (FBL_F32, torch.float32), "bf16": (FBL_BF16, torch.bfloat16), "f16": (FBL_F16, torch.float16)}
 
 EXPORTED = ("fbl_geometry_check", "fbl_plan_create", "fbl_plan_destroy", "fb_lisa_forward",
-            "fb_lisa_backproject", "fb_lisa_step", "fbl_timing_enable", "fbl_timing_read", "fbl_last_error")
+            "fb_lisa_backproject", "fb_lisa_step", "fbl_mlp_workspace_bytes", "fbl_mlp_forward",
+            "fbl_mlp_loss_grad", "fbl_mlp_adam", "fbl_timing_enable", "fbl_timing_read", "fbl_last_error")
+MLP_IN, MLP_HIDDEN = 5, 64
+MLP_NPARAMS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 KERNELS = ("forward", "transpose", "finalize", "prescale", "backproject", "step")  # FBL_K_* order
 
 
@@ -57,12 +60,19 @@ def _load() -> ctypes.CDLL:
     lib.fb_lisa_backproject.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_double, P, P]
     lib.fb_lisa_step.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  P, P, P]
+    lib.fbl_mlp_workspace_bytes.argtypes = [ctypes.c_int64]
+    lib.fbl_mlp_workspace_bytes.restype = ctypes.c_size_t
+    lib.fbl_mlp_forward.argtypes = [P, P, ctypes.c_int64, P, P]
+    lib.fbl_mlp_loss_grad.argtypes = [P, P, P, ctypes.c_int64, P, P, P, P]
+    lib.fbl_mlp_adam.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, P]
     lib.fbl_timing_enable.argtypes = [P, ctypes.c_int]
     lib.fbl_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.fbl_last_error.argtypes = []
     lib.fbl_last_error.restype = ctypes.c_char_p
     for name in ("fbl_geometry_check", "fbl_plan_create", "fb_lisa_forward", "fb_lisa_backproject",
-                 "fb_lisa_step", "fbl_timing_enable", "fbl_timing_read"):
+                 "fb_lisa_step", "fbl_mlp_forward", "fbl_mlp_loss_grad", "fbl_mlp_adam", "fbl_timing_enable",
+                 "fbl_timing_read"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -225,3 +235,61 @@ def fb_lisa_step(plan: Plan, x: torch.Tensor, g: torch.Tensor, alpha: float, mu:
     _check(lib.fb_lisa_step(plan.handle, x.data_ptr(), g.data_ptr(), float(alpha), float(mu), float(lo),
                             float(hi), xbar.data_ptr(), red.data_ptr(), _stream(stream)))
     return xbar, red
+
+
+# -- learned initial step: perceptron kernels --------------------------------------------
+
+def _need_vec(t: torch.Tensor, name: str, n: int):
+    _need(t, name, torch.float32)
+    if t.numel() != n:
+        raise ValueError("%s must have %d elements, got %d" % (name, n, t.numel()))
+
+
+def mlp_workspace(n: int, device=None) -> torch.Tensor:
+    """A device workspace for mlp_loss_grad on n samples (256-byte aligned)."""
+    nbytes = int(lib.fbl_mlp_workspace_bytes(int(n)))
+    w = torch.empty(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+    off = (-w.data_ptr()) % 256
+    return w[off:off + nbytes]
+
+
+def mlp_forward(params: torch.Tensor, X: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
+    """out[i] = MLP(X[i]) (X FP32 [n][5])."""
+    _need_vec(params, "params", MLP_NPARAMS)
+    _need(X, "X", torch.float32)
+    if X.dim() != 2 or X.shape[1] != MLP_IN:
+        raise ValueError("X must be [n][%d]" % MLP_IN)
+    n = X.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=X.device)
+    _need_vec(out, "out", n)
+    _check(lib.fbl_mlp_forward(params.data_ptr(), X.data_ptr(), n, out.data_ptr(), _stream(stream)))
+    return out
+
+
+def mlp_loss_grad(params: torch.Tensor, X: torch.Tensor, t: torch.Tensor, work: torch.Tensor,
+                  grad: Optional[torch.Tensor] = None, loss: Optional[torch.Tensor] = None, stream=None):
+    """grad = d/dparams of 1/(2n) sum (MLP(X) - t)^2; loss[0] = sum (MLP(X) - t)^2 (FP64)."""
+    _need_vec(params, "params", MLP_NPARAMS)
+    _need(X, "X", torch.float32)
+    n = X.shape[0]
+    _need_vec(t, "t", n)
+    if work.numel() < int(lib.fbl_mlp_workspace_bytes(n)):
+        raise ValueError("workspace too small for %d samples" % n)
+    if grad is None:
+        grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=X.device)
+    _need_vec(grad, "grad", MLP_NPARAMS)
+    if loss is not None:
+        _need(loss, "loss", torch.float64)
+    _check(lib.fbl_mlp_loss_grad(params.data_ptr(), X.data_ptr(), t.data_ptr(), n, grad.data_ptr(), _ptr(loss),
+                                 work.data_ptr(), _stream(stream)))
+    return grad
+
+
+def mlp_adam(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float,
+             beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
+    """One in-place Adam update of params (state m, v)."""
+    for t, name in ((params, "params"), (grad, "grad"), (m, "m"), (v, "v")):
+        _need_vec(t, name, MLP_NPARAMS)
+    _check(lib.fbl_mlp_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), int(step), float(lr),
+                            float(beta1), float(beta2), float(eps), _stream(stream)))

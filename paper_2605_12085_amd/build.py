@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfblisa.so")
-SOURCES = ["plan.hip", "forward.hip", "backproject.hip", "step.hip"]
+SOURCES = ["plan.hip", "forward.hip", "backproject.hip", "step.hip", "mlp.hip"]
 ARCH = os.environ.get("FBL_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

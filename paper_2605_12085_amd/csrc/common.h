@@ -116,6 +116,13 @@ hipError_t launch_backproject(const fbl_plan *p, const float *rw, const ViewList
 hipError_t launch_step(const fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo,
                        double hi, void *xbar, int64_t *n_partials_used, hipStream_t st);
 
+size_t mlp_workspace_bytes(int64_t n);
+hipError_t launch_mlp_forward(const float *prm, const float *X, int64_t n, float *out, hipStream_t st);
+hipError_t launch_mlp_loss_grad(const float *prm, const float *X, const float *t, int64_t n, float *grad,
+                                double *loss, void *work, hipStream_t st);
+hipError_t launch_mlp_adam(float *prm, const float *grad, float *m, float *v, int64_t step, double lr, double b1,
+                           double b2, double eps, hipStream_t st);
+
 int step_blocks(const fbl_plan *p);
 int backproject_tile();   // in-slice tile extent of the backprojection (voxels)
 

@@ -530,6 +530,44 @@ int fb_lisa_step(fbl_plan *p, const void *x, const float *g, double alpha, doubl
     return ok();
 }
 
+size_t fbl_mlp_workspace_bytes(int64_t n) { return n < 1 ? 0 : mlp_workspace_bytes(n); }
+
+int fbl_mlp_forward(const float *params, const float *X, int64_t n, float *out, void *stream)
+{
+    if (!params || !X || !out) return fail(FBL_E_INVALID, "params, X and out must be non-NULL");
+    if (n < 1 || n > ((int64_t)1 << 31)) return fail(FBL_E_RANGE, "n = %lld outside [1, 2^31]", (long long)n);
+    if (!aligned16(params) || !aligned16(X) || !aligned16(out))
+        return fail(FBL_E_INVALID, "arrays must be 16-byte aligned");
+    hipError_t e = launch_mlp_forward(params, X, n, out, (hipStream_t)stream);
+    return e == hipSuccess ? ok() : hip_fail(e, "MLP forward launch");
+}
+
+int fbl_mlp_loss_grad(const float *params, const float *X, const float *t, int64_t n, float *grad, double *loss_dev,
+                      void *work, void *stream)
+{
+    if (!params || !X || !t || !grad || !work) return fail(FBL_E_INVALID, "params, X, t, grad and work must be non-NULL");
+    if (n < 1 || n > ((int64_t)1 << 31)) return fail(FBL_E_RANGE, "n = %lld outside [1, 2^31]", (long long)n);
+    if (!aligned16(params) || !aligned16(X) || !aligned16(t) || !aligned16(grad) || (loss_dev && !aligned8(loss_dev)))
+        return fail(FBL_E_INVALID, "arrays must be 16-byte aligned and loss_dev 8-byte aligned");
+    if (((uintptr_t)work & 255u) != 0) return fail(FBL_E_INVALID, "work must be 256-byte aligned");
+    hipError_t e = launch_mlp_loss_grad(params, X, t, n, grad, loss_dev, work, (hipStream_t)stream);
+    return e == hipSuccess ? ok() : hip_fail(e, "MLP gradient launch");
+}
+
+int fbl_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step, double lr, double beta1,
+                 double beta2, double eps, void *stream)
+{
+    if (!params || !grad || !m || !v) return fail(FBL_E_INVALID, "params, grad, m and v must be non-NULL");
+    if (step < 1) return fail(FBL_E_RANGE, "step must be >= 1");
+    if (!(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0) ||
+        !std::isfinite(lr) || !std::isfinite(eps))
+        return fail(FBL_E_INVALID, "need lr > 0, 0 <= beta1, beta2 < 1, eps > 0");
+    if (!aligned16(params) || !aligned16(grad) || !aligned16(m) || !aligned16(v))
+        return fail(FBL_E_INVALID, "arrays must be 16-byte aligned");
+    hipError_t e = launch_mlp_adam(params, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+    return e == hipSuccess ? ok() : hip_fail(e, "Adam launch");
+}
+
 int fbl_timing_enable(fbl_plan *p, int on)
 {
     if (!p) return fail(FBL_E_INVALID, "plan is NULL");

@@ -111,12 +111,18 @@ class FBLisa:
         self.scal = torch.zeros(8, dtype=torch.float64, device=dev)
         self.host = torch.zeros(8, dtype=torch.float64).pin_memory()
         self.k = 0
+        self.epoch = 0
         self.history: List[Iteration] = []
 
     # -- one iteration (Steps 2b-2d) ---------------------------------------------------
-    def iterate(self, views: Sequence[int], alpha_init: Optional[float] = None, epoch: int = 0,
+    def iterate(self, views: Sequence[int], alpha_init=None, epoch: int = 0,
                 decisions: Optional[Sequence[bool]] = None) -> Iteration:
+        """One iteration (Steps 2b-2d) on the given views.  ``alpha_init`` is the first
+        trial step: None (alpha_0), a number, or a callable proposer(self) evaluated once
+        the forward projection and the backprojection are enqueued (so a proposer that
+        runs device work overlaps them)."""
         t0 = time.perf_counter()
+        self.epoch = epoch
         v = np.asarray(views, dtype=np.int32)
         B = len(v)
         f_scale = self.n / (2.0 * B)
@@ -124,7 +130,11 @@ class FBLisa:
         plan = self.plan
         fb_lisa_forward(plan, self.x, v, self.b, r, self.scal[0:1], f_scale)
         fb_lisa_backproject(plan, r, v, self.n / float(B), self.g)
+        if callable(alpha_init):
+            alpha_init = alpha_init(self)
         alpha = self.alpha0 if alpha_init is None else float(alpha_init)
+        if not alpha > 0.0:
+            raise ValueError("initial step must be > 0, got %r" % alpha)
         trials: List[Trial] = []
         stream = torch.cuda.current_stream()
         for j in range(self.j_max + 1):
@@ -157,7 +167,7 @@ class FBLisa:
 
     # -- Algorithm 1 --------------------------------------------------------------------
     def run(self, perms: np.ndarray, max_iters: Optional[int] = None,
-            alpha_init: Optional[Callable[["FBLisa"], float]] = None,
+            alpha_init: Optional[Callable[["FBLisa"], Optional[float]]] = None,
             callback: Optional[Callable[["FBLisa", Iteration], None]] = None,
             decisions: Optional[Sequence[Sequence[bool]]] = None) -> torch.Tensor:
         """Epochs t = 1..T; epoch t runs ceil(n/N_t) iterations on the first N_t views of
@@ -169,8 +179,8 @@ class FBLisa:
             for k in range(k_hat, k_hat + iters):
                 if max_iters is not None and k >= max_iters:
                     return self.x
-                a0 = None if alpha_init is None else alpha_init(self)
-                it = self.iterate(perms[k][:nt], a0, epoch=t, decisions=None if decisions is None else decisions[k])
+                it = self.iterate(perms[k][:nt], alpha_init, epoch=t,
+                                  decisions=None if decisions is None else decisions[k])
                 if callback is not None:
                     callback(self, it)
             k_hat += iters

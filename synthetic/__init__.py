@@ -384,3 +384,15 @@ def random_volume(g: Geometry, seed: int, lo=0.0, hi=0.02, dtype=np.float32) -> 
 def random_projections(g: Geometry, n: int, seed: int, scale=1.0, dtype=np.float32) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return (scale * rng.standard_normal((n, g.nv, g.nu))).astype(dtype)
+
+
+def mlp_params(seed: int, n_in: int = 5, n_hidden: int = 64) -> np.ndarray:
+    """Seeded initial parameters of the step-proposal perceptron, flat FP32 in the order
+    W1[h][n_in], b1[h], W2[h][h], b2[h], w3[h], b3: weights uniform in +-sqrt(6/fan_in),
+    biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.uniform(-1, 1, (n_hidden, n_in)) * math.sqrt(6.0 / n_in), np.zeros(n_hidden),
+             rng.uniform(-1, 1, (n_hidden, n_hidden)) * math.sqrt(6.0 / n_hidden), np.zeros(n_hidden),
+             rng.uniform(-1, 1, n_hidden) * math.sqrt(6.0 / n_hidden), np.zeros(1)]
+    return np.concatenate([q.ravel() for q in parts]).astype(np.float32)
+
