@@ -49,12 +49,14 @@ struct LineRegs {
     float a[KB], b[KB];
 };
 
+// Waves per SIMD the register budget is held to: short lines fit four (<= 128 VGPRs).
+constexpr int fp_waves(int kb) { return kb <= 16 ? 4 : kb <= 32 ? 3 : 2; }
+
 template <typename TV, typename TB, int KB>
-__global__ __launch_bounds__(kThreads) void fp_kernel(const TV *__restrict__ x, const TV *__restrict__ xt, Geo geo,
-                                                      DeviceTables tab, ViewList vl, int first,
-                                                      const TB *__restrict__ b, float *__restrict__ y,
-                                                      double *__restrict__ partials, int blocks_per_view,
-                                                      int want_loss)
+__global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
+    const TV *__restrict__ x, const TV *__restrict__ xt, Geo geo, DeviceTables tab, ViewList vl, int first,
+    const TB *__restrict__ b, float *__restrict__ y, double *__restrict__ partials, int blocks_per_view,
+    int want_loss)
 {
     __shared__ float line[KB * kThreads];
     __shared__ double red[4];
@@ -83,12 +85,13 @@ __global__ __launch_bounds__(kThreads) void fp_kernel(const TV *__restrict__ x, 
     const TV *__restrict__ vol = cp.axis == 0 ? xt : x;
     const int64_t zstride = (int64_t)geo.nx * geo.ny;
     const int64_t sstride = cp.axis == 0 ? geo.ny : geo.nx;
-    const double *__restrict__ Vrow = tab.rowV;
     const float xs = (float)cp.xi1;
-    // per-ray eta slope per slice; row values are re-read (cached) at each refresh
-    float es[kRows], eb[kRows];
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) es[r] = (float)(cp.t1 * Vrow[min(rr0 + r, geo.nv - 1)]);
+    // Rows are equally spaced in eta: row rr0 + r sits at eta = cz + tau * (V0 + r * dvz),
+    // with V0 the vertical index slope of row rr0.  Per slice the thread keeps the first
+    // row's line coordinate A and the row-to-row step D = tau * dvz; ray r is at A + r D.
+    const double V0 = tab.rowV[rr0];
+    const float es0 = (float)(cp.t1 * V0);              // dA per slice
+    const float ds = (float)(cp.t1 * (double)geo.dvz);  // dD per slice
     float *__restrict__ my = line + tid;
     // the longest slice march in the block decides the trip count of every lane
     int na_max = na;
@@ -104,12 +107,11 @@ __global__ __launch_bounds__(kThreads) void fp_kernel(const TV *__restrict__ x, 
         const int ib = (int)floor(xmin) - 1;
         const float xf = (float)(xb - (double)ib);
         const double tb = fma((double)m0, cp.t1, cp.t0);
-        const double e0 = fma(tb, Vrow[rr0], geo.cz);
-        const double emin = fmin(e0, e0 + (double)(kChunk - 1) * cp.t1 * Vrow[rr0]);
+        const double e0 = fma(tb, V0, geo.cz);
+        const double emin = fmin(e0, e0 + (double)(kChunk - 1) * cp.t1 * V0);
         const int k0 = (int)floor(emin) - 1;
-#pragma unroll
-        for (int r = 0; r < kRows; ++r)
-            eb[r] = (float)(fma(tb, Vrow[min(rr0 + r, geo.nv - 1)], geo.cz) - (double)k0);
+        const float eb0 = (float)(e0 - (double)k0);       // A at the chunk's first slice
+        const float db = (float)(tb * (double)geo.dvz);   // D at the chunk's first slice
         float part[kRows];
 #pragma unroll
         for (int r = 0; r < kRows; ++r) part[r] = 0.0f;
@@ -128,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void fp_kernel(const TV *__restrict__ x, 
                 else if (i0 == nb - 1) { p = nb - 2; S.wa = 0.0f; S.wb = 1.0f - ax; }
                 else { p = 0; S.wa = 0.0f; S.wb = 0.0f; }
             }
-            const float ef = fmaf(fl, es[0], eb[0]);
+            const float ef = fmaf(fl, es0, eb0);
             S.ka = (int)(ef - 1e-3f);
             S.kz = k0 + S.ka;
             S.inside = S.kz >= 0 && S.kz + KB <= geo.nz;
@@ -178,10 +180,12 @@ __global__ __launch_bounds__(kThreads) void fp_kernel(const TV *__restrict__ x, 
             // vertical interpolation per ray from the thread's line
             if (s < sc) {
                 const float fl = (float)s;
+                const float A = fmaf(fl, es0, eb0);
+                const float D = fmaf(fl, ds, db);
                 float *__restrict__ base = my - P.ka * kThreads;
 #pragma unroll
                 for (int r = 0; r < kRows; ++r) {
-                    const float e = fmaf(fl, es[r], eb[r]);
+                    const float e = fmaf((float)r, D, A);
                     const int j = (int)e;
                     const float ay = __builtin_amdgcn_fractf(e);
                     const float t0 = base[j * kThreads];
