@@ -37,23 +37,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+KERNEL_SOURCES = {"fp_kernel": "forward.hip", "bp_kernel": "backproject.hip"}
+
+
+def kernel_source_hash(kernel: str) -> str:
     h = hashlib.sha256()
-    for f in ("forward.hip", "common.h", "device_util.h"):
+    for f in (KERNEL_SOURCES[kernel], "device_util.h"):
         with open(os.path.join(ROOT, "paper_2605_12085_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(cfg: str, bytes_per_launch: float):
-    """HBM bytes per forward launch from the committed rocprofv3 counter summary, if it
+def measured_traffic(kernel: str, cfg: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "fp_kernel_%s_pmc.json" % cfg)
+    path = os.path.join(ROOT, "profiles", "%s_%s_pmc.json" % (kernel, cfg))
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("kernel_source_hash") != kernel_source_hash(kernel):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -94,6 +97,81 @@ def cpu_baseline(g, b32, perms, B, alpha0, beta, lo, hi, min_seconds=12.0, max_i
     }
 
 
+def train_step_proposer(fbl, syn, n_runs=200, iters=2000, lr=3e-3):
+    """The learned-step perceptron, trained on the GPU from the traces of n_runs seeded plain
+    FB-LISA runs of the 64^3 / 60-view / 6-view-batch workload."""
+    import torch
+    rec = fbl.TraceRecorder()
+    g = syn.config_geometry("c1")
+    cfg = syn.CONFIGS["c1"]
+    for rep in range(n_runs):
+        seed = 1000 + rep
+        ells, _ = syn.phantom(g, cfg["k"], seed=seed, hi=cfg["hi"])
+        b = syn.add_noise(syn.ellipsoid_line_integrals(g, ells, np.arange(g.n_views)), 0.01, seed=seed + 1)
+        perms = syn.view_permutations(g.n_views, 200, seed=seed + 2)
+        run = fbl.FBLisa(g, torch.from_numpy(b.astype(np.float32)).cuda(), n0=cfg["batch"], epochs=cfg["epochs"],
+                         lo=cfg["lo"], hi=cfg["hi"])
+        run.run(perms, callback=rec)
+    X, t = rec.arrays()
+    model = fbl.StepModel(syn.mlp_params(7))
+    curve = model.fit(X, t, iters=iters, lr=lr)
+    return model, len(t), curve
+
+
+def time_to_rmse(fbl, g, cfg, b32, xt, perms, proposer):
+    """Wall time to the reconstruction error of the plain FP32 run: the plain FP32 run sets
+    RMSE* (its error after the configured epochs) and is timed to its first iterate at or
+    below RMSE*; the learned-step run with BF16 volume and FP16 data storage is timed to
+    the same target.  Device-synchronised host clock; RMSE evaluations excluded."""
+    import torch
+    xt_dev = torch.from_numpy(xt.astype(np.float32)).cuda()
+
+    class Reached(Exception):
+        pass
+
+    def go(b_dev, vol_dtype, alpha_init, target):
+        run = fbl.FBLisa(g, b_dev, n0=cfg["batch"], epochs=cfg["epochs"], lo=cfg["lo"], hi=cfg["hi"],
+                         vol_dtype=vol_dtype)
+        st = {"excluded": 0.0, "t": [], "rmse": []}
+
+        def cb(r, it):
+            t_in = time.perf_counter()
+            st["t"].append(t_in - st["t0"] - st["excluded"])   # the iterate is complete (read back)
+            e = float(torch.sqrt(torch.mean((r.x.float() - xt_dev) ** 2)))
+            st["rmse"].append(e)
+            st["excluded"] += time.perf_counter() - t_in
+            if target is not None and e <= target:
+                raise Reached()
+
+        torch.cuda.synchronize()
+        st["t0"] = time.perf_counter()
+        try:
+            run.run(perms, alpha_init=alpha_init, callback=cb)
+        except Reached:
+            pass
+        return run.history, st
+
+    hist_p, st_p = go(torch.from_numpy(b32).cuda(), "f32", None, None)
+    target = st_p["rmse"][-1]
+    k_p = next(i for i, e in enumerate(st_p["rmse"]) if e <= target) + 1
+    hist_l, st_l = go(torch.from_numpy(b32).cuda().half(), "bf16", proposer, target)
+    k_l = len(hist_l)
+    reached = st_l["rmse"][-1] <= target
+
+    def summary(hist, st, k):
+        h = hist[:k]
+        return {"seconds": round(st["t"][k - 1], 4), "iterations": k, "rmse": st["rmse"][k - 1],
+                "fp_calls_per_iter": round(float(np.mean([2 + it.backtracks for it in h])), 3),
+                "backtracks_per_iter": round(float(np.mean([it.backtracks for it in h])), 3)}
+
+    return {
+        "rmse_target": target,
+        "plain_f32": summary(hist_p, st_p, k_p),
+        "learned_bf16": dict(summary(hist_l, st_l, k_l), reached=reached),
+        "speedup": round(st_p["t"][k_p - 1] / st_l["t"][k_l - 1], 3) if reached else None,
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +179,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2", help="workload (c1..c4); the default is the metric's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-time-to-rmse", action="store_true",
+                    help="skip the time-to-RMSE comparison (learned step + BF16 storage against plain FP32)")
     ap.add_argument("--probe", action="store_true",
                     help="counter-collection run: 3 forward, 1 backprojection, 1 step call of the workload, then "
                          "a plain 512 MiB device copy whose FETCH_SIZE/WRITE_SIZE calibrate the counters")
@@ -176,11 +256,16 @@ def main(argv=None):
     t_bp_call = (kt["backproject"][0] + kt["prescale"][0]) / n_bp * 1e-3
     t_st = kt["step"][0] / kt["step"][1] * 1e-3                # step_kernel alone
 
-    # roofline of the dominant kernel (forward projection): the per-view block model,
-    # each view reads the volume once and writes its n_p FP32 values
-    bytes_fp = B * (g.d * 4 + 4 * g.n_p)
-    achieved = bytes_fp / t_fp / 1e9
-    traffic = measured_traffic(args.config, bytes_fp)
+    # roofline of the dominant kernel (the projector kernel with the larger share of the
+    # timed region): the per-view block model, each view reads the volume once and writes
+    # (forward) or reads (backprojection) its n_p FP32 values
+    bytes_view = B * (g.d * 4 + 4 * g.n_p)
+    share = {"fp_kernel": kt["forward"][0], "bp_kernel": kt["backproject"][0]}
+    dominant = max(share, key=share.get)
+    t_dom = t_fp if dominant == "fp_kernel" else t_bp
+    achieved = bytes_view / t_dom / 1e9
+    other = "bp_kernel" if dominant == "fp_kernel" else "fp_kernel"
+    t_other = t_bp if dominant == "fp_kernel" else t_fp
 
     rec = {
         "metric": METRIC,
@@ -208,13 +293,19 @@ def main(argv=None):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "kernel": "fp_kernel (forward projection with residual and loss partials)",
-            "bytes_per_launch": bytes_fp,
+            "traffic": measured_traffic(dominant, args.config),
+            "kernel": dominant,
+            "bytes_per_launch": bytes_view,
+            "share_of_timed_region": round(share[dominant] / (wall * 1e3), 4),
+        },
+        "roofline_other": {
+            "kernel": other,
+            "achieved": round(bytes_view / t_other / 1e9, 1),
+            "frac": round(bytes_view / t_other / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(other, args.config),
+            "share_of_timed_region": round(share[other] / (wall * 1e3), 4),
         },
         "kernel_us": kernel_us,
-        "backproject_roofline": {"achieved": round(bytes_fp / t_bp / 1e9, 1), "frac": round(bytes_fp / t_bp / 1e9 /
-                                                                                          HBM_PEAK_GBS, 4)},
         "step_hbm": {"bytes_per_launch": 12 * g.d, "achieved": round(12 * g.d / t_st / 1e9, 1),
                      "frac": round(12 * g.d / t_st / 1e9 / HBM_PEAK_GBS, 4)},
         "per_call_ms": {"forward": round(t_fp_call * 1e3, 4), "backproject": round(t_bp_call * 1e3, 4),
@@ -223,6 +314,17 @@ def main(argv=None):
         "calls": {"forward": n_fp, "backproject": n_bp, "step": kt["step"][1]},
         "mean_backtracks": float(np.mean([it.backtracks for it in timed])),
     }
+    if not args.no_time_to_rmse:
+        log("training the step proposer (200 plain runs of the 64^3 workload) ...")
+        t_tr = time.perf_counter()
+        model, n_samples, curve = train_step_proposer(fbl, syn)
+        log("trained on %d samples in %.1f s (loss %.3e -> %.3e)" % (n_samples, time.perf_counter() - t_tr,
+                                                                    curve[0], curve[-1]))
+        n_it = cfg["epochs"] * math.ceil(g.n_views / B)
+        perms_run = syn.view_permutations(g.n_views, n_it, seed=seed + 2)
+        tt = time_to_rmse(fbl, g, cfg, b32, xt, perms_run, fbl.LearnedStep(model))
+        tt["proposer"] = "5-64-64-1 perceptron trained on %d iterations of 200 seeded 64^3 runs" % n_samples
+        rec["time_to_rmse"] = tt
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(g, b32, perms, B, alpha0, beta, cfg["lo"], cfg["hi"])

@@ -11,15 +11,19 @@
 // included: voxels outside the volume are never written).
 //
 // A workgroup owns a 16 x 16 x 16 voxel tile and loops over the batch's views.  For a
-// view, each axis class of its columns and each half of the tile's slices it
-//   1. finds, per slice, the detector columns whose ray plane crosses the tile;
+// view and each axis class of its columns it
+//   1. finds, per slice of the tile, the detector columns whose ray plane crosses the
+//      tile, and lists the (slice, column) pairs with their xi and ray parameter;
+// then, for each half of the tile's z-range,
 //   2. stages the weighted residual of those columns and of the rows that reach the
-//      tile's z-range in LDS, and lets one lane per (slice, column) pair gather that
-//      pair's 16-entry z-profile from the few rows within one voxel of each k (rows
-//      are equally spaced in eta, so the candidates are consecutive);
-//   3. lets each thread gather its 16 voxels from the profiles of the columns whose
-//      xi lies within one voxel (binary search: xi is monotone along the row).
+//      half's z-range in LDS (zero-padded above and below);
+//   3. gathers each pair's 8-entry z-profile from the few rows within one voxel of each
+//      k (rows are equally spaced in eta, so the candidates are consecutive), a quarter
+//      of the work items per pair so that every lane has about the same load;
+//   4. lets every thread add to its voxel column (m, q) the profiles of the columns whose
+//      xi lies within one voxel (binary search: xi is monotone along the slice's pairs).
 #include <climits>
+#include <type_traits>
 
 #include "common.h"
 #include "device_util.h"
@@ -28,12 +32,15 @@ namespace fbl {
 
 namespace {
 
-constexpr int kTQ = 16;        // tile extent along x and along y
+constexpr int kTQ = 16;        // tile extent along x and along y (and slices per class pass)
 constexpr int kTK = 16;        // tile extent along z (voxels per thread)
-constexpr int kSP = 8;         // slices per pass (two passes cover the tile)
+constexpr int kKH = 8;         // z-entries per half pass
+constexpr int kKQ = 4;         // z-entries per profile work item
 constexpr int kThreads = 256;
 constexpr int kRowPad = 8;     // zero rows above and below the staged residual window
-constexpr int kWinRows = 48;   // staged rows per column (longer spans read global memory)
+constexpr int kWinRows = 32;   // staged rows per column (longer spans read global memory)
+constexpr int kWinStride = kWinRows + 2 * kRowPad + 1;   // odd: lanes on adjacent columns use distinct banks
+constexpr int kWinExtra = 16;  // columns the 16 slices' ranges may add to one slice's
 
 // rw = grad_scale * w * r: the per-ray path length per slice folded into the residual.
 __global__ __launch_bounds__(256) void prescale_kernel(const float *__restrict__ r, Geo geo, DeviceTables tab,
@@ -60,20 +67,22 @@ __device__ __forceinline__ float column_of(const Geo &geo, const ViewParam &vp, 
     return geo.sdd * lat / dep / geo.du + geo.cu;
 }
 
-// z-profile of one (slice, column) pair: Z(kk) = sum_t hat(e_t - kk) * val(t), where row t
-// of the pair's source has e_t = a0 + rowz * t (eta relative to the tile's first z).  The
-// NC = ceil(2 / rowz) candidates of each kk start at the first row with e_t > kk - 1.
+// Part of the z-profile of one (slice, column) pair: Z(kk) = sum_t hat(e_t - kk) * val(t)
+// for kk = kk0 .. kk0 + kKQ - 1, where row t of the pair's source has e_t = a0 + rowz * t
+// (eta relative to the pass's first z).  The NC = ceil(2 / rowz) candidates of each kk
+// start at the first row with e_t > kk - 1.
 template <int NC, typename Fetch>
-__device__ __forceinline__ void pair_profile(float a0, float rowz, int t_lo, int t_hi, Fetch fetch, float *zout,
-                                             int zstride)
+__device__ __forceinline__ void pair_profile(float a0, float rowz, int kk0, int t_lo, int t_hi, Fetch fetch,
+                                             float *zout, int zstride)
 {
     const float inv = 1.0f / rowz;
 #pragma unroll
-    for (int kk = 0; kk < kTK; ++kk) {
-        const float rho = ((float)kk - 1.0f - a0) * inv;   // e_t = kk - 1 at t = rho
+    for (int j = 0; j < kKQ; ++j) {
+        const float kk = (float)(kk0 + j);
+        const float rho = (kk - 1.0f - a0) * inv;   // e_t = kk - 1 at t = rho
         int tf = (int)floorf(rho) + 1;
         tf = min(max(tf, t_lo), t_hi);
-        float d = fmaf(rowz, (float)tf, a0 - (float)kk);
+        float d = fmaf(rowz, (float)tf, a0 - kk);
         float s = 0.0f;
 #pragma unroll
         for (int t = 0; t < NC; ++t) {
@@ -81,26 +90,28 @@ __device__ __forceinline__ void pair_profile(float a0, float rowz, int t_lo, int
             s = fmaf(w, fetch(tf + t), s);
             d += rowz;
         }
-        zout[kk * zstride] = s;
+        zout[(kk0 + j) * zstride] = s;
     }
 }
 
 template <int WP, int NC>
-__global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const float *__restrict__ rw, Geo geo, DeviceTables tab,
-                                                      ViewList vl, int nb, int first, int accumulate,
-                                                      float *__restrict__ g)
+__global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const float *__restrict__ rw, Geo geo,
+                                                                        DeviceTables tab, ViewList vl, int nb,
+                                                                        int first, int accumulate,
+                                                                        float *__restrict__ g)
 {
-    constexpr int NPAIR = kSP * WP;
-    constexpr int kWinCols = WP + 3 * kSP;          // column union of a pass (per-slice ranges shift)
-    constexpr int kWinStride = kWinRows + 2 * kRowPad + 1;   // odd: staging writes avoid bank conflicts
-    static_assert(NPAIR <= 2 * kThreads, "a thread owns at most two pairs");
-    __shared__ float Z[kTK * NPAIR];                // Z[k][pair]: z-profile of each (slice, column) pair
-    __shared__ float xiq[NPAIR];                    // xi of the pair's column on its slice, relative to q0
-    __shared__ float win[kWinCols * kWinStride];    // residual window, column-major, zero-padded rows
-    __shared__ int colA[kSP], colN[kSP];            // first column and column count per slice
-    __shared__ float dirS[kSP];                     // +1 if xi increases along the slice's columns, else -1
+    constexpr int NPM = kTQ * WP;                     // pair slots: 16 slices x WP columns
+    constexpr int kWinCols = WP + kWinExtra;          // column union of the 16 slices
+    constexpr int kWinSize = kWinCols * kWinStride;
+    __shared__ float Z[kKH * NPM];                    // Z[k][pair]: half-pass z-profile of each pair
+    __shared__ float xiq[NPM];                        // xi of the pair's column on its slice, minus q0
+    __shared__ double ptau[NPM];                      // ray parameter there; 0 if xi misses the tile
+    __shared__ short pcr[NPM];                        // the pair's column minus the class window's c0
+    __shared__ float win[kWinSize];                   // residual window, column-major, zero-padded rows
+    __shared__ int colA[kTQ], colN[kTQ], pfx[kTQ];    // per slice: first column, count, first pair
 
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int tiles_x = (geo.nx + kTQ - 1) / kTQ, tiles_y = (geo.ny + kTQ - 1) / kTQ;
     const int tile = blockIdx.x;
     const int i0 = (tile % tiles_x) * kTQ;
@@ -141,176 +152,171 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
             const int na = axis == 0 ? geo.nx : geo.ny;
             const int mt0 = axis == 0 ? i0 : j0;       // first slice of the tile
             const int q0 = axis == 0 ? j0 : i0;        // first in-slice index of the tile
-            for (int half = 0; half < kTQ / kSP; ++half) {
-                __syncthreads();   // the previous pass's readers are done with the shared arrays
-                // 1. per-slice column ranges
-                if (tid < kSP) {
-                    const int mg = mt0 + half * kSP + tid;
-                    int a = 0, n = 0;
-                    if (mg < na) {
-                        const float fm = (float)mg;
-                        float u0, u1;
-                        if (axis == 0) {
-                            const float X = (fm - cxv) * geo.hx;
-                            u0 = column_of(geo, vp, X, ((float)(q0 - 1) - cyv) * geo.hy);
-                            u1 = column_of(geo, vp, X, ((float)(q0 + kTQ) - cyv) * geo.hy);
-                        } else {
-                            const float Y = (fm - cyv) * geo.hy;
-                            u0 = column_of(geo, vp, ((float)(q0 - 1) - cxv) * geo.hx, Y);
-                            u1 = column_of(geo, vp, ((float)(q0 + kTQ) - cxv) * geo.hx, Y);
-                        }
-                        const float lo = fminf(u0, u1), hi = fmaxf(u0, u1);
-                        a = max(cl0, (int)floorf(fmaxf(lo, -4.0f)) - 1);
-                        const int b = min(cl1, (int)ceilf(fminf(hi, (float)geo.nu + 4.0f)) + 1);
-                        n = min(WP, max(0, b - a + 1));
+            __syncthreads();   // the previous class's readers are done with the shared arrays
+            // 1. per-slice column ranges
+            if (tid < kTQ) {
+                const int mg = mt0 + tid;
+                int a = 0, n = 0;
+                if (mg < na) {
+                    const float fm = (float)mg;
+                    float u0, u1;
+                    if (axis == 0) {
+                        const float X = (fm - cxv) * geo.hx;
+                        u0 = column_of(geo, vp, X, ((float)(q0 - 1) - cyv) * geo.hy);
+                        u1 = column_of(geo, vp, X, ((float)(q0 + kTQ) - cyv) * geo.hy);
+                    } else {
+                        const float Y = (fm - cyv) * geo.hy;
+                        u0 = column_of(geo, vp, ((float)(q0 - 1) - cxv) * geo.hx, Y);
+                        u1 = column_of(geo, vp, ((float)(q0 + kTQ) - cxv) * geo.hx, Y);
                     }
-                    colA[tid] = a;
-                    colN[tid] = n;
+                    const float lo = fminf(u0, u1), hi = fmaxf(u0, u1);
+                    a = max(cl0, (int)floorf(fmaxf(lo, -4.0f)) - 1);
+                    const int b = min(cl1, (int)ceilf(fminf(hi, (float)geo.nu + 4.0f)) + 1);
+                    n = min(WP, max(0, b - a + 1));
                 }
-                __syncthreads();
-                // 2a. the pass's detector window: columns [c0, c1] (union of the slices'
-                //     ranges) and every row that can reach z in (k0 - 1, k0 + kTK).  The
-                //     ray parameter tau is monotone along a detector row (it is inversely
-                //     proportional to the column's D_a, which is affine in the column) and
-                //     affine in the slice index, so its extremes over the pass sit at the
-                //     corner (first/last column, first/last slice) pairs; the detector row
-                //     of a given height is monotone in tau.
-                int c0 = INT_MAX, c1 = -1;
+                colA[tid] = a;
+                colN[tid] = n;
+            }
+            __syncthreads();
+            // the class window's columns [c0, c1] (union of the slices' ranges), the pair
+            // count and each slice's first pair (every thread forms them alike)
+            int c0 = INT_MAX, c1 = -1, NP = 0;
 #pragma unroll
-                for (int m = 0; m < kSP; ++m)
-                    if (colN[m] > 0) {
-                        c0 = min(c0, colA[m]);
-                        c1 = max(c1, colA[m] + colN[m] - 1);
-                    }
-                if (c1 < 0) continue;   // uniform across the block
+            for (int m = 0; m < kTQ; ++m) {
+                const int n = colN[m];
+                if (tid == m) pfx[m] = NP;
+                if (n > 0) {
+                    c0 = min(c0, colA[m]);
+                    c1 = max(c1, colA[m] + n - 1);
+                }
+                NP += n;
+            }
+            if (c1 < 0) continue;   // uniform across the block
+            // 2. pair geometry: xi for the voxel gather, the ray parameter for the profile
+            for (int p = tid; p < NP; p += kThreads) {
+                int m = 0, end = colN[0];
+                while (p >= end) end += colN[++m];   // p < NP, so m stays below kTQ
+                const int c = colA[m] + (p - (end - colN[m]));
+                const ColParam cp = cols[c];
+                const double fm = (double)(mt0 + m);
+                const float xl = (float)(fma(fm, cp.xi1, cp.xi0) - (double)q0);
+                xiq[p] = xl;
+                ptau[p] = (xl > -1.0f && xl < (float)kTQ) ? fma(fm, cp.t1, cp.t0) : 0.0;
+                pcr[p] = (short)(c - c0);
+            }
+            // extremes of the ray parameter over the class's pairs: tau is monotone along
+            // a detector row (inversely proportional to the column's D_a, which is affine
+            // in the column) and affine in the slice, so they sit at the corner (first/last
+            // column, first/last slice) pairs; a detector row of a given height is monotone
+            // in tau.  Bounds are taken in FP32 (rounding is far below the one-row margins).
+            float imin, imax;
+            {
+                const int mA = mt0, mB = min(mt0 + kTQ - 1, na - 1);
+                const ColParam ca = cols[c0], cb = cols[c1];
+                const double t00 = fma((double)mA, ca.t1, ca.t0), t01 = fma((double)mB, ca.t1, ca.t0);
+                const double t10 = fma((double)mA, cb.t1, cb.t0), t11 = fma((double)mB, cb.t1, cb.t0);
+                imin = 1.0f / (float)(fmax(fmax(t00, t01), fmax(t10, t11)) * dvz);
+                imax = 1.0f / (float)(fmin(fmin(t00, t01), fmin(t10, t11)) * dvz);
+            }
+            const int nC = c1 - c0 + 1;
+            __syncthreads();   // pair tables complete
+
+            auto half_pass = [&](auto hc) {
+                constexpr int h = decltype(hc)::value;
+                const int kb = k0 + h * kKH;   // first z of this half
+                // detector rows that can reach z in (kb - 1, kb + kKH)
                 int r0, nR;
                 {
-                    const int mA = mt0 + half * kSP, mB = min(mA + kSP - 1, na - 1);
-                    const ColParam ca = cols[c0], cb = cols[c1];
-                    const double t00 = fma((double)mA, ca.t1, ca.t0), t01 = fma((double)mB, ca.t1, ca.t0);
-                    const double t10 = fma((double)mA, cb.t1, cb.t0), t11 = fma((double)mB, cb.t1, cb.t0);
-                    // bounds in FP32 (rounding is far below the one-row margins)
-                    const float imin = 1.0f / (float)(fmax(fmax(t00, t01), fmax(t10, t11)) * dvz);
-                    const float imax = 1.0f / (float)(fmin(fmin(t00, t01), fmin(t10, t11)) * dvz);
-                    const float e0 = (float)((double)(k0 - 1) - geo.cz), e1 = (float)((double)(k0 + kTK) - geo.cz);
+                    const float e0 = (float)((double)(kb - 1) - geo.cz), e1 = (float)((double)(kb + kKH) - geo.cz);
                     const float a = e0 * imin, b = e0 * imax, c = e1 * imin, d = e1 * imax;
                     const float rlo = fminf(fminf(a, b), fminf(c, d)) + geo.cv;
                     const float rhi = fmaxf(fmaxf(a, b), fmaxf(c, d)) + geo.cv;
                     r0 = max(0, (int)floorf(rlo) - 1);
                     nR = min(geo.nv - 1, (int)ceilf(rhi) + 1) - r0 + 1;
                 }
-                if (nR <= 0) continue;   // uniform
-                const int nC = c1 - c0 + 1;
+                if (nR <= 0) return;   // uniform across the block
                 const bool staged = nR <= kWinRows && nC <= kWinCols;
-                // staging: every load is issued before the LDS writes; consecutive lanes
-                // read consecutive columns (contiguous in memory); addresses are clamped
-                // into the detector and entries outside the window are written as 0
-                constexpr int kWinSize = kWinCols * kWinStride;
-                constexpr int kIt = (kWinSize + kThreads - 1) / kThreads;
-                float stv[kIt];
                 if (staged) {
+                    // window row t holds detector row r0 - kRowPad + t; rows outside
+                    // [kRowPad, kRowPad + nR) are zero.  Lanes run along columns (contiguous
+                    // in memory), waves along rows; four rows' loads are issued together.
+                    for (int col = lane; col < nC; col += 64) {
+                        const float *__restrict__ src = rwv + c0 + col;   // detector row 0 of the column
+                        float *__restrict__ dst = win + col * kWinStride;
+                        for (int t = wave; t < kWinStride; t += 16) {
+                            float v[4];
 #pragma unroll
-                    for (int it = 0; it < kIt; ++it) {
-                        const int e = tid + it * kThreads;
-                        const int col = e % kWinCols, row = e / kWinCols;
-                        const int r = min(max(r0 + row - kRowPad, 0), geo.nv - 1);
-                        const int cc = min(c0 + col, geo.nu - 1);
-                        stv[it] = rwv[(int64_t)r * geo.nu + cc];
-                    }
-                }
-                // 2b. pair geometry: xi for step 3 and the ray parameter for the profile
-                double ptau[2] = {0.0, 0.0};
-                int pcol[2] = {0, 0};
-                bool pin[2] = {false, false};
-#pragma unroll
-                for (int sI = 0; sI < 2; ++sI) {
-                    const int pr = tid + sI * kThreads;
-                    if (pr < NPAIR) {
-                        const int ml = pr % kSP, cl = pr / kSP;
-                        float xl = 3.0e38f;
-                        if (cl < colN[ml]) {
-                            const int c = colA[ml] + cl;
-                            const ColParam cp = cols[c];
-                            const double fm = (double)(mt0 + half * kSP + ml);
-                            xl = (float)(fma(fm, cp.xi1, cp.xi0) - (double)q0);
-                            if (xl > -1.0f && xl < (float)kTQ) {
-                                pin[sI] = true;
-                                pcol[sI] = c;
-                                ptau[sI] = fma(fm, cp.t1, cp.t0);
+                            for (int u = 0; u < 4; ++u) {
+                                const int tu = t + 4 * u;
+                                v[u] = (tu >= kRowPad && tu < kRowPad + nR)
+                                           ? src[(int64_t)(r0 - kRowPad + tu) * geo.nu]
+                                           : 0.0f;
                             }
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                if (t + 4 * u < kWinStride) dst[t + 4 * u] = v[u];
                         }
-                        xiq[pr] = xl;
                     }
                 }
-                if (staged) {
-#pragma unroll
-                    for (int it = 0; it < kIt; ++it) {
-                        const int e = tid + it * kThreads;
-                        if (e < kWinSize) {
-                            const int col = e % kWinCols, row = e / kWinCols;
-                            const bool inside = row >= kRowPad && row < kRowPad + nR && col < nC;
-                            win[col * kWinStride + row] = inside ? stv[it] : 0.0f;
-                        }
+                __syncthreads();   // window staged; the previous half's gather of Z is done
+                // 3. profiles: item (pair, quarter of the half's z-range)
+                for (int it = tid; it < (kKH / kKQ) * NP; it += kThreads) {
+                    int kq = 0, pr = it;
+                    while (pr >= NP) { pr -= NP; ++kq; }
+                    const double tau = ptau[pr];
+                    if (tau == 0.0) continue;
+                    const float rz = (float)(tau * dvz);
+                    if (staged) {
+                        const float a0 = (float)(geo.cz + tau * ((double)(r0 - kRowPad) - (double)geo.cv) * dvz -
+                                                 (double)kb);
+                        const float *__restrict__ wc = win + pcr[pr] * kWinStride;
+                        pair_profile<NC>(a0, rz, kq * kKQ, 0, kWinStride - NC, [&](int t) { return wc[t]; }, Z + pr,
+                                         NPM);
+                    } else {
+                        // detector rows directly (rows outside [0, nv) do not exist)
+                        const float a0 = (float)(geo.cz + tau * (0.0 - (double)geo.cv) * dvz - (double)kb);
+                        const float *__restrict__ src = rwv + c0 + pcr[pr];
+                        const int64_t nu = geo.nu;
+                        pair_profile<NC>(a0, rz, kq * kKQ, 0, max(0, geo.nv - NC),
+                                         [&](int t) {
+                                             const float v = src[(int64_t)min(t, geo.nv - 1) * nu];
+                                             return t < geo.nv ? v : 0.0f;
+                                         },
+                                         Z + pr, NPM);
                     }
                 }
                 __syncthreads();
-                if (tid < kSP) {
-                    const int n = colN[tid];
-                    dirS[tid] = (n >= 2 && xiq[(n - 1) * kSP + tid] < xiq[tid]) ? -1.0f : 1.0f;
-                }
-                // 2c. one lane per pair gathers the pair's z-profile
-#pragma unroll
-                for (int sI = 0; sI < 2; ++sI) {
-                    const int pr = tid + sI * kThreads;
-                    if (pr < NPAIR && pin[sI]) {
-                        const double rowz = ptau[sI] * dvz;
-                        const float rz = (float)rowz;
-                        if (staged) {
-                            // source row t = window row (t - kRowPad) = detector row r0 + t - kRowPad
-                            const float a0 = (float)(geo.cz + ptau[sI] * ((double)(r0 - kRowPad) - (double)geo.cv) * dvz -
-                                                     (double)k0);
-                            const float *__restrict__ wc = win + (pcol[sI] - c0) * kWinStride;
-                            pair_profile<NC>(a0, rz, 0, kWinStride - NC, [&](int t) { return wc[t]; }, Z + pr, NPAIR);
-                        } else {
-                            // detector row t directly (rows outside [0, nv) do not exist)
-                            const float a0 = (float)(geo.cz + ptau[sI] * (0.0 - (double)geo.cv) * dvz - (double)k0);
-                            const float *__restrict__ src = rwv + pcol[sI];
-                            const int64_t nu = geo.nu;
-                            pair_profile<NC>(a0, rz, 0, max(0, geo.nv - NC),
-                                             [&](int t) {
-                                                 const float v = src[(int64_t)min(t, geo.nv - 1) * nu];
-                                                 return t < geo.nv ? v : 0.0f;
-                                             },
-                                             Z + pr, NPAIR);
-                        }
-                    }
-                }
-                __syncthreads();
-                // 3. each thread gathers its voxel column (m, q) from the columns near q
-                const int ml = (axis == 0 ? ti : tj) - half * kSP;
-                if (ml >= 0 && ml < kSP) {
-                    const float q = (float)(axis == 0 ? tj : ti);
-                    const int n = colN[ml];
-                    const float s = dirS[ml];
-                    // first pair with s*xi > s*q - 1 (s*xi increases with the pair index)
+                // 4. each thread gathers its voxel column (m, q) from the columns near q
+                const int m = axis == 0 ? ti : tj;
+                const float q = (float)(axis == 0 ? tj : ti);
+                const int n = colN[m];
+                if (n > 0) {
+                    const float *__restrict__ xs = xiq + pfx[m];
+                    const float sgn = (n >= 2 && xs[n - 1] < xs[0]) ? -1.0f : 1.0f;
+                    // first pair with sgn*xi > sgn*q - 1 (sgn*xi increases along the slice)
                     int lo = 0, hi = n;
                     while (lo < hi) {
                         const int mid = (lo + hi) >> 1;
-                        if (s * xiq[mid * kSP + ml] > s * q - 1.0f) hi = mid;
+                        if (sgn * xs[mid] > sgn * q - 1.0f) hi = mid;
                         else lo = mid + 1;
                     }
-                    for (int p = lo; p < n; ++p) {
-                        const float xv = xiq[p * kSP + ml];
-                        if (!(s * xv < s * q + 1.0f)) break;
+                    for (int pp = lo; pp < n; ++pp) {
+                        const float xv = xs[pp];
+                        if (!(sgn * xv < sgn * q + 1.0f)) break;
                         const float w = 1.0f - fabsf(xv - q);
                         if (w > 0.0f) {
-                            const float *__restrict__ zp = Z + (p * kSP + ml);
+                            const float *__restrict__ zp = Z + pfx[m] + pp;
 #pragma unroll
-                            for (int kk = 0; kk < kTK; ++kk) acc[kk] = fmaf(w, zp[kk * NPAIR], acc[kk]);
+                            for (int kk = 0; kk < kKH; ++kk)
+                                acc[h * kKH + kk] = fmaf(w, zp[kk * NPM], acc[h * kKH + kk]);
                         }
                     }
                 }
-            }
+            };
+            // half 1 overwrites Z only after the barrier that follows its staging, which every
+            // thread reaches once its half-0 gather is done
+            half_pass(std::integral_constant<int, 0>{});
+            half_pass(std::integral_constant<int, 1>{});
         }
     }
     const int i = i0 + ti, j = j0 + tj;

@@ -122,6 +122,24 @@ def test_backproject_c1_all_voxels(fbl, orc):
     _cmp_vol(gg, ref, what="backprojection c1")
 
 
+def test_fine_detector_rows_forward_and_backprojection(fbl, orc):
+    # detector rows 0.6 voxel apart at the detector (about 0.3 voxel at the volume): the
+    # backprojection's residual window for half a tile's z-range exceeds its LDS window on
+    # some passes, which then read the residual from device memory
+    g = syn.Geometry(24, 24, 20, 1.0, 1.0, 1.0, 36, 60, 1.5, 0.6, 300.0, 600.0, 12)
+    rng = np.random.default_rng(16)
+    views = np.arange(g.n_views, dtype=np.int32)
+    x = rng.uniform(0, 1, g.vol_shape).astype(np.float32)
+    r = rng.standard_normal((len(views), g.nv, g.nu)).astype(np.float32)
+    y_ref = orc.forward(g, x.astype(np.float64), views)
+    g_ref = orc.backproject(g, r.astype(np.float64), views)
+    with fbl.Plan(g) as plan:
+        y = fbl.fb_lisa_forward(plan, _t(x), views).cpu().numpy()
+        gg = fbl.fb_lisa_backproject(plan, _t(r), views, grad_scale=1.0).cpu().numpy()
+    _cmp_views(y, y_ref, what="forward fine rows")
+    _cmp_vol(gg, g_ref, what="backprojection fine rows")
+
+
 def test_adjoint_identity_on_gpu(fbl):
     import torch
     g = syn.Geometry(40, 36, 30, 1.0, 1.0, 1.0, 60, 44, 1.4, 1.4, 400.0, 800.0, 16)
