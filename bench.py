@@ -157,6 +157,8 @@ def time_to_rmse(fbl, g, cfg, b32, xt, perms, proposer):
     hist_l, st_l = go(torch.from_numpy(b32).cuda().half(), "bf16", proposer, target)
     k_l = len(hist_l)
     reached = st_l["rmse"][-1] <= target
+    hist_f, st_f = go(torch.from_numpy(b32).cuda(), "f32", proposer, target)
+    k_f = len(hist_f)
 
     def summary(hist, st, k):
         h = hist[:k]
@@ -168,7 +170,75 @@ def time_to_rmse(fbl, g, cfg, b32, xt, perms, proposer):
         "rmse_target": target,
         "plain_f32": summary(hist_p, st_p, k_p),
         "learned_bf16": dict(summary(hist_l, st_l, k_l), reached=reached),
+        "learned_f32": dict(summary(hist_f, st_f, k_f), reached=st_f["rmse"][-1] <= target),
         "speedup": round(st_p["t"][k_p - 1] / st_l["t"][k_l - 1], 3) if reached else None,
+    }
+
+
+def paper_shaped_run(fbl, syn, seconds: float, views: int = 72, n: int = 560, n0: int = 8, seed: int = 5600):
+    """The paper's own variant on a synthetic stand-in for its walnut scan: an n^3 volume,
+    `views` projections over [0, 2 pi), 2% noise, R = mu ||x||_1 + nonnegativity, the
+    growing mini-batch of Step 1 (C = N_0 eps_{ceil(n_theta/N_0)}), run for a wall-clock
+    budget.  Reports the batch sizes per epoch and the relative error against time."""
+    import torch
+    h = 64.0 / n
+    det = (3 * n) // 2
+    g = syn.Geometry(n, n, n, h, h, h, det, det, 96.0 / det, 96.0 / det, 500.0, 1000.0, views)
+    t0 = time.perf_counter()
+    ells, xt = syn.phantom(g, 30, seed=seed, sub=2)
+    b = syn.add_noise(syn.ellipsoid_line_integrals(g, ells, np.arange(views)), 0.02, seed=seed + 1)
+    log("paper-shaped data (%d^3, %d views, %dx%d detector): %.1f s" % (n, views, det, det, time.perf_counter() - t0))
+    bd = torch.from_numpy(b.astype(np.float32)).cuda()
+    del b
+    xt_dev = torch.from_numpy(xt.astype(np.float32)).cuda()
+    nrm = float(torch.linalg.vector_norm(xt_dev.double()))
+    # mu: 2% of the largest entry of the full-batch gradient at x = 0
+    with fbl.Plan(g, max_batch=views) as plan:
+        r0 = fbl.fb_lisa_forward(plan, torch.zeros_like(xt_dev), np.arange(views), bd)
+        g0 = fbl.fb_lisa_backproject(plan, r0, np.arange(views))
+        mu = 0.02 * float(g0.abs().max())
+        del r0, g0
+    C = fbl.growing_batch_C(views, n0)
+    perms = syn.view_permutations(views, 200000, seed=seed + 2)
+    run = fbl.FBLisa(g, bd, n0=n0, epochs=100000, mu=mu, C=C)
+    st = {"excluded": 0.0, "series": [], "next": 0.0}
+
+    class Budget(Exception):
+        pass
+
+    def cb(r, it):
+        t_in = time.perf_counter()
+        el = t_in - st["t0"] - st["excluded"]
+        if el >= st["next"] or el >= seconds:
+            re = float(torch.linalg.vector_norm((r.x - xt_dev).double())) / nrm
+            st["series"].append({"t": round(el, 3), "k": it.k + 1, "epoch": it.epoch, "batch": len(it.batch),
+                                 "re": re})
+            st["next"] = el + max(0.5, seconds / 60.0)
+        st["excluded"] += time.perf_counter() - t_in
+        if el >= seconds:
+            raise Budget()
+
+    torch.cuda.synchronize()
+    st["t0"] = time.perf_counter()
+    try:
+        run.run(perms, callback=cb)
+    except Budget:
+        pass
+    per_epoch = {}
+    for it in run.history:
+        per_epoch.setdefault(it.epoch, len(it.batch))
+    return {
+        "mode": "paper-shaped growth run",
+        "workload": "%d^3 ellipsoid phantom (30), %d views over [0, 2pi), %dx%d detector, 2%% noise, "
+                    "mu = %.4g (2%% of max |grad f(0)|), nonnegativity, N_0 = %d, growth C = %.4g"
+                    % (n, views, det, det, mu, n0, C),
+        "seconds": seconds,
+        "iterations": len(run.history),
+        "epochs": max(per_epoch) if per_epoch else 0,
+        "batch_per_epoch": [per_epoch[e] for e in sorted(per_epoch)],
+        "mean_backtracks": float(np.mean([it.backtracks for it in run.history])),
+        "series": st["series"],
+        "final_re": st["series"][-1]["re"] if st["series"] else None,
     }
 
 
@@ -184,6 +254,9 @@ def main(argv=None):
     ap.add_argument("--probe", action="store_true",
                     help="counter-collection run: 3 forward, 1 backprojection, 1 step call of the workload, then "
                          "a plain 512 MiB device copy whose FETCH_SIZE/WRITE_SIZE calibrate the counters")
+    ap.add_argument("--paper-run", type=float, default=0.0, metavar="SECONDS",
+                    help="instead of the benchmark: the paper's growing-batch variant with mu > 0 on a 560^3 / "
+                         "72-view synthetic stand-in, for this many seconds")
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -198,6 +271,9 @@ def main(argv=None):
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.paper_run > 0:
+        print(json.dumps(paper_shaped_run(fbl, syn, args.paper_run)), flush=True)
+        return 0
     cfg = syn.CONFIGS[args.config]
     g = syn.config_geometry(args.config)
     B = cfg["batch"]

@@ -125,9 +125,13 @@ class StepModel:
 
 class LearnedStep:
     """Proposer for FBLisa.run(alpha_init=...): alpha_0 at the first iteration, then
-    alpha_0 * beta^j with j the predicted number of halvings rounded to the nearest
-    integer and clipped to [0, j_max] (a proposal on the method's own step grid, never
-    above alpha_0)."""
+    alpha_0 * beta^j with j the predicted number of halvings rounded down and clipped to
+    [0, j_max] -- a proposal on the method's own step grid, never above alpha_0.
+
+    Rounding down errs towards the larger step: a proposal above the step the plain
+    search would accept costs one more trial (one forward projection) and then lands on
+    that same step, while a proposal below it is accepted as is and shortens the step,
+    which costs iterations."""
 
     def __init__(self, model: StepModel, j_max: int = 20):
         self.model = model
@@ -148,6 +152,6 @@ class LearnedStep:
         self._y.copy_(self._yd, non_blocking=True)
         torch.cuda.current_stream().synchronize()
         log_ratio = float(self._y[0])
-        j = int(round(log_ratio / math.log10(run.beta))) if math.isfinite(log_ratio) else 0
+        j = int(math.floor(log_ratio / math.log10(run.beta))) if math.isfinite(log_ratio) else 0
         j = min(max(j, 0), self.j_max)
         return run.alpha0 * run.beta ** j

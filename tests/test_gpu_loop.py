@@ -65,6 +65,36 @@ def test_replay_and_free_run(orc):
     assert orc.rmse(xf, xt) < orc.rmse(np.zeros_like(xt), xt)
 
 
+def test_growth_schedule_with_l1_term_replay(orc):
+    # the paper's own variant: the mini-batch grows by Step 1 (C = N_0 eps_{ceil(n/N_0)})
+    # and R = mu ||x||_1 + nonnegativity with mu > 0; the GPU follows the oracle's
+    # decisions and must keep its iterates within 1e-4 and use the same batch sizes
+    import torch
+    import paper_2605_12085_amd as fbl
+    g, xt, b32, perms = _problem(seed=310)
+    epochs, n0 = 4, 4
+    C = orc.growth_C(g.n_views, n0)
+    b64 = b32.astype(np.float64)
+    # mu: a small fraction of the largest gradient entry at x = 0 (full batch)
+    _, g0, _ = orc.objective_and_gradient(g, np.zeros(g.vol_shape), b64, np.arange(g.n_views))
+    mu = 0.02 * float(np.abs(g0).max())
+    xs_orc = []
+    x_orc, rec = orc.fblisa(g, b64, epochs=epochs, n0=n0, perms=perms, mu=mu, C=C,
+                            callback=lambda k, x, r: xs_orc.append(x.copy()))
+    sizes = [len(r.batch) for r in rec]
+    assert sizes[0] == n0 and max(sizes) > n0            # the batch grows
+    assert all(a <= b for a, b in zip(sizes, sizes[1:]))  # and never shrinks
+    assert np.mean(x_orc == 0.0) > 0.05                   # the l1 term zeroes voxels
+    decisions = [[t.accepted for t in r.trials] for r in rec]
+    bd = torch.from_numpy(b32).cuda()
+    xs_gpu = []
+    run = fbl.FBLisa(g, bd, n0=n0, epochs=epochs, mu=mu, C=C)
+    run.run(perms, decisions=decisions, callback=lambda s, it: xs_gpu.append(s.x.cpu().numpy().astype(np.float64)))
+    assert [len(it.batch) for it in run.history] == sizes
+    for k, (xg, xo) in enumerate(zip(xs_gpu, xs_orc)):
+        assert np.linalg.norm(xg - xo) <= 1e-4 * np.linalg.norm(xo), k
+
+
 def test_fixed_point_on_gpu(orc):
     # noise-free data of a nonnegative x_true with mu = 0: starting at x_true the
     # gradient is (numerically) zero and every iterate stays at x_true (appendix: a
