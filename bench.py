@@ -129,9 +129,9 @@ def time_to_rmse(fbl, g, cfg, b32, xt, perms, proposer):
     class Reached(Exception):
         pass
 
-    def go(b_dev, vol_dtype, alpha_init, target):
+    def go(b_dev, vol_dtype, alpha_init, target, sr_seed=None):
         run = fbl.FBLisa(g, b_dev, n0=cfg["batch"], epochs=cfg["epochs"], lo=cfg["lo"], hi=cfg["hi"],
-                         vol_dtype=vol_dtype)
+                         vol_dtype=vol_dtype, sr_seed=sr_seed)
         st = {"excluded": 0.0, "t": [], "rmse": []}
 
         def cb(r, it):
@@ -154,11 +154,13 @@ def time_to_rmse(fbl, g, cfg, b32, xt, perms, proposer):
     hist_p, st_p = go(torch.from_numpy(b32).cuda(), "f32", None, None)
     target = st_p["rmse"][-1]
     k_p = next(i for i, e in enumerate(st_p["rmse"]) if e <= target) + 1
-    hist_l, st_l = go(torch.from_numpy(b32).cuda().half(), "bf16", proposer, target)
+    b16 = torch.from_numpy(b32).cuda().half()
+    hist_l, st_l = go(b16, "bf16", proposer, target, sr_seed=2024)
     k_l = len(hist_l)
     reached = st_l["rmse"][-1] <= target
+    hist_n, st_n = go(b16, "bf16", proposer, target)
+    hist_h, st_h = go(b16, "f16", proposer, target, sr_seed=2024)
     hist_f, st_f = go(torch.from_numpy(b32).cuda(), "f32", proposer, target)
-    k_f = len(hist_f)
 
     def summary(hist, st, k):
         h = hist[:k]
@@ -169,8 +171,12 @@ def time_to_rmse(fbl, g, cfg, b32, xt, perms, proposer):
     return {
         "rmse_target": target,
         "plain_f32": summary(hist_p, st_p, k_p),
-        "learned_bf16": dict(summary(hist_l, st_l, k_l), reached=reached),
-        "learned_f32": dict(summary(hist_f, st_f, k_f), reached=st_f["rmse"][-1] <= target),
+        "learned_bf16": dict(summary(hist_l, st_l, k_l), reached=reached,
+                             storage="BF16 volume (stochastic rounding), FP16 data"),
+        "learned_bf16_nearest": dict(summary(hist_n, st_n, len(hist_n)), reached=st_n["rmse"][-1] <= target),
+        "learned_f16": dict(summary(hist_h, st_h, len(hist_h)), reached=st_h["rmse"][-1] <= target,
+                            storage="FP16 volume (stochastic rounding), FP16 data"),
+        "learned_f32": dict(summary(hist_f, st_f, len(hist_f)), reached=st_f["rmse"][-1] <= target),
         "speedup": round(st_p["t"][k_p - 1] / st_l["t"][k_l - 1], 3) if reached else None,
     }
 

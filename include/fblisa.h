@@ -188,6 +188,17 @@ enum {
 FBL_API int fbl_timing_enable(fbl_plan *plan, int on);
 FBL_API int fbl_timing_read(fbl_plan *plan, double ms[FBL_K_COUNT], int64_t launches[FBL_K_COUNT]);
 
+/* fb_lisa_step with stochastic rounding of the trial point to the storage type (for 16-bit
+ * iterates, so that updates below half a unit in the last place are not lost on average).
+ * A value v between adjacent representable numbers a < v < a + q becomes a + q with
+ * probability (v - a) / q: it goes up iff u < (v - a) / q, where u = (z >> 11) * 2^-53 and
+ * z is output number i+1 of SplitMix64 (Steele, Lea and Flood, 2014) seeded with `key`,
+ * i the voxel's linear index.  Representable values are unchanged.  The result depends
+ * only on (x, g, alpha, mu, lo, hi, key): a caller replays it with the same key and
+ * decorrelates trials with different keys.  Arguments and errors as fb_lisa_step. */
+FBL_API int fb_lisa_step_sr(fbl_plan *plan, const void *x, const float *g, double alpha, double mu, double lo,
+                            double hi, uint64_t key, void *xbar, double *red_dev, void *stream);
+
 /* Message of the last failed call on this thread ("" if none); valid until the next
  * call on the same thread. */
 FBL_API const char *fbl_last_error(void);

@@ -293,17 +293,61 @@ def round_storage(v, storage) -> np.ndarray:
     raise ValueError("unknown storage %r" % (storage,))
 
 
-def prox_step(x, grad, alpha: float, mu: float, lo: float = 0.0, hi: float = math.inf, storage=None):
+_SPLITMIX_GAMMA = 0x9E3779B97F4A7C15
+_PRECISION = {"f32": (24, -126), "bf16": (8, -126), "f16": (11, -14)}   # significant bits, min normal exponent
+
+
+def splitmix64(key: int, counters) -> np.ndarray:
+    """Outputs number counters+1 of SplitMix64 (Steele, Lea and Flood, 2014) seeded with
+    ``key``: the state after c+1 steps is key + (c+1) * gamma (mod 2^64), mixed by the
+    generator's finaliser.  Used as a counter-based generator: voxel i draws output i+1."""
+    c = np.asarray(counters, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(key & 0xFFFFFFFFFFFFFFFF) + (c + np.uint64(1)) * np.uint64(_SPLITMIX_GAMMA)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def trial_key(seed: int, k: int, j: int) -> int:
+    """Rounding key of line-search trial j of iteration k: (seed << 32) + (k << 6) + j
+    (mod 2^64); j stays below 64 (at most 51 trials)."""
+    return ((int(seed) << 32) + (int(k) << 6) + int(j)) & 0xFFFFFFFFFFFFFFFF
+
+
+def round_stochastic(v, storage: str, key: int) -> np.ndarray:
+    """Stochastic rounding of FP64 values to a storage type: a value between the adjacent
+    representable numbers a < v < a + q goes up with probability (v - a) / q, decided by
+    r < (v - a) / q with r = (splitmix64(key, i) >> 11) * 2^-53 for the value's flat index
+    i; representable values are unchanged.  All steps are exact in FP64 (q is a power of
+    two, a a multiple of q within one q of v)."""
+    v = _f64(v)
+    P, emin = _PRECISION[storage]
+    flat = v.ravel()
+    out = flat.copy()
+    fin = np.isfinite(flat) & (flat != 0)
+    _, e = np.frexp(flat[fin])                       # |v| in [2^(e-1), 2^e)
+    q = np.ldexp(1.0, np.maximum(e - 1, emin) - (P - 1))
+    a = np.floor(flat[fin] / q) * q
+    p = (flat[fin] - a) / q
+    r = (splitmix64(key, np.nonzero(fin)[0]) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    out[fin] = np.where(r < p, a + q, a)
+    return out.reshape(v.shape)
+
+
+def prox_step(x, grad, alpha: float, mu: float, lo: float = 0.0, hi: float = math.inf, storage=None,
+              key: Optional[int] = None):
     """Trial point of Algorithm 1 Step 2c and the inner products of (2.3).
 
     xbar = prox(x - alpha grad); with ``storage`` ("f32", "bf16", "f16" or a numpy
     dtype) the trial point is rounded to that storage type, as a stored iterate would
-    be, before d = xbar - x is formed.  Returns (xbar, <grad, d>, ||d||^2, ||grad||^2).
+    be, before d = xbar - x is formed: to nearest, or stochastically with ``key`` (see
+    round_stochastic).  Returns (xbar, <grad, d>, ||d||^2, ||grad||^2).
     """
     x64, g64 = _f64(x), _f64(grad)
     xbar = prox(x64 - alpha * g64, alpha, mu, lo, hi)
     if storage is not None:
-        xbar = round_storage(xbar, storage)
+        xbar = round_storage(xbar, storage) if key is None else round_stochastic(xbar, storage, key)
     d = xbar - x64
     return xbar, float(np.dot(g64.ravel(), d.ravel())), float(np.dot(d.ravel(), d.ravel())), \
         float(np.dot(g64.ravel(), g64.ravel()))
@@ -333,13 +377,15 @@ def sufficient_decrease(f_bar: float, f0: float, inner: float, sq: float, alpha:
 
 def line_search(fun: Callable[[np.ndarray], float], x: np.ndarray, f0: float, grad: np.ndarray,
                 alpha_init: float, beta: float, mu: float, lo: float, hi: float, j_max: int = 50,
-                decide: Optional[Callable[[int], bool]] = None, storage=None):
+                decide: Optional[Callable[[int], bool]] = None, storage=None,
+                key: Optional[Callable[[int], int]] = None):
     """Backtracking of Algorithm 1, Step 2c.
 
     Starting from alpha_init, forms xbar = prox(x - alpha grad) and accepts the first
     alpha for which (2.3) holds; otherwise alpha <- beta * alpha.  ``decide`` (replay
     mode) overrides the accept/reject decision of trial j.  ``storage`` rounds each
-    trial point to a storage type (see round_storage) before it is used.
+    trial point to a storage type before it is used: to nearest (round_storage), or
+    stochastically with the key ``key(j)`` of trial j (round_stochastic).
     Returns (alpha, xbar, f_bar, trials).
     """
     alpha = alpha_init
@@ -347,7 +393,7 @@ def line_search(fun: Callable[[np.ndarray], float], x: np.ndarray, f0: float, gr
     for j in range(j_max + 1):
         xbar = prox(x - alpha * grad, alpha, mu, lo, hi)
         if storage is not None:
-            xbar = round_storage(xbar, storage)
+            xbar = round_storage(xbar, storage) if key is None else round_stochastic(xbar, storage, key(j))
         dlt = xbar - x
         inner = float(np.dot(grad.ravel(), dlt.ravel()))
         sq = float(np.dot(dlt.ravel(), dlt.ravel()))
@@ -420,13 +466,14 @@ def fblisa(g, b_full, *, epochs: int, n0: int, alpha0: float = 1e-3, beta: float
            x0: Optional[np.ndarray] = None, perms: Optional[np.ndarray] = None,
            j_max: int = 50, decisions: Optional[Sequence[Sequence[bool]]] = None,
            alpha_init: Optional[Callable[[int], float]] = None,
-           max_iters: Optional[int] = None, callback=None, storage=None):
+           max_iters: Optional[int] = None, callback=None, storage=None, sr_seed: Optional[int] = None):
     """Algorithm 1 (FB-LISA) in FP64 with n = n_theta (one f_i per projection angle).
 
     perms[k] is a permutation of the views for iteration k; the mini-batch is its
     first N_t entries.  ``decisions`` (replay) forces the accept/reject outcome of
     each trial.  ``alpha_init(k)`` replaces alpha_0 as the first trial step.
-    ``storage`` keeps the iterates rounded to a storage type (the arithmetic stays FP64).
+    ``storage`` keeps the iterates rounded to a storage type (the arithmetic stays FP64),
+    to nearest or, with ``sr_seed``, stochastically with trial_key(sr_seed, k, j).
     Returns (x, records).
     """
     n = g.n_views
@@ -451,7 +498,7 @@ def fblisa(g, b_full, *, epochs: int, n0: int, alpha0: float = 1e-3, beta: float
                 dec = lambda j, dk=dk: dk[j]
             alpha, xbar, f_bar, trials = line_search(
                 lambda z: objective(g, z, b_full, views), x, f0, grad, a0, beta, mu, lo, hi, j_max, dec,
-                storage)
+                storage, None if sr_seed is None else (lambda j, k=k: trial_key(sr_seed, k, j)))
             records.append(IterRecord(t, k, np.asarray(views).copy(), f0, alpha, len(trials) - 1, trials))
             x = xbar
             if callback is not None:

@@ -24,7 +24,7 @@ _VOL_DTYPES = {"f32": (FBL_F32, torch.float32), "bf16": (FBL_BF16, torch.bfloat1
 _PROJ_DTYPES = {"f32": (FBL_F32, torch.float32), "bf16": (FBL_BF16, torch.bfloat16), "f16": (FBL_F16, torch.float16)}
 
 EXPORTED = ("fbl_geometry_check", "fbl_plan_create", "fbl_plan_destroy", "fb_lisa_forward",
-            "fb_lisa_backproject", "fb_lisa_step", "fbl_mlp_workspace_bytes", "fbl_mlp_forward",
+            "fb_lisa_backproject", "fb_lisa_step", "fb_lisa_step_sr", "fbl_mlp_workspace_bytes", "fbl_mlp_forward",
             "fbl_mlp_loss_grad", "fbl_mlp_adam", "fbl_timing_enable", "fbl_timing_read", "fbl_last_error")
 MLP_IN, MLP_HIDDEN = 5, 64
 MLP_NPARAMS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
@@ -60,6 +60,8 @@ def _load() -> ctypes.CDLL:
     lib.fb_lisa_backproject.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_double, P, P]
     lib.fb_lisa_step.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  P, P, P]
+    lib.fb_lisa_step_sr.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_uint64, P, P, P]
     lib.fbl_mlp_workspace_bytes.argtypes = [ctypes.c_int64]
     lib.fbl_mlp_workspace_bytes.restype = ctypes.c_size_t
     lib.fbl_mlp_forward.argtypes = [P, P, ctypes.c_int64, P, P]
@@ -71,7 +73,7 @@ def _load() -> ctypes.CDLL:
     lib.fbl_last_error.argtypes = []
     lib.fbl_last_error.restype = ctypes.c_char_p
     for name in ("fbl_geometry_check", "fbl_plan_create", "fb_lisa_forward", "fb_lisa_backproject",
-                 "fb_lisa_step", "fbl_mlp_forward", "fbl_mlp_loss_grad", "fbl_mlp_adam", "fbl_timing_enable",
+                 "fb_lisa_step", "fb_lisa_step_sr", "fbl_mlp_forward", "fbl_mlp_loss_grad", "fbl_mlp_adam", "fbl_timing_enable",
                  "fbl_timing_read"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
@@ -220,8 +222,10 @@ def fb_lisa_backproject(plan: Plan, r: torch.Tensor, views: Sequence[int], grad_
 
 def fb_lisa_step(plan: Plan, x: torch.Tensor, g: torch.Tensor, alpha: float, mu: float = 0.0, lo: float = 0.0,
                  hi: float = math.inf, xbar: Optional[torch.Tensor] = None, red: Optional[torch.Tensor] = None,
-                 stream=None):
-    """xbar = prox(x - alpha g); red = [<g, xbar - x>, ||xbar - x||^2, ||g||^2] (FP64)."""
+                 stream=None, key: Optional[int] = None):
+    """xbar = prox(x - alpha g); red = [<g, xbar - x>, ||xbar - x||^2, ||g||^2] (FP64).  With a
+    ``key`` (an unsigned 64-bit integer) xbar is rounded to the storage type stochastically
+    (fb_lisa_step_sr), else to nearest."""
     _need(x, "x", plan.vol_torch, plan.vol_shape)
     _need(g, "g", torch.float32, plan.vol_shape)
     if xbar is None:
@@ -232,8 +236,13 @@ def fb_lisa_step(plan: Plan, x: torch.Tensor, g: torch.Tensor, alpha: float, mu:
     _need(red, "red", torch.float64)
     if red.numel() < 3:
         raise ValueError("red needs three elements")
-    _check(lib.fb_lisa_step(plan.handle, x.data_ptr(), g.data_ptr(), float(alpha), float(mu), float(lo),
-                            float(hi), xbar.data_ptr(), red.data_ptr(), _stream(stream)))
+    if key is None:
+        _check(lib.fb_lisa_step(plan.handle, x.data_ptr(), g.data_ptr(), float(alpha), float(mu), float(lo),
+                                float(hi), xbar.data_ptr(), red.data_ptr(), _stream(stream)))
+    else:
+        _check(lib.fb_lisa_step_sr(plan.handle, x.data_ptr(), g.data_ptr(), float(alpha), float(mu), float(lo),
+                                   float(hi), int(key) & 0xFFFFFFFFFFFFFFFF, xbar.data_ptr(), red.data_ptr(),
+                                   _stream(stream)))
     return xbar, red
 
 

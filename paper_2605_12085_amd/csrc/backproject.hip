@@ -69,28 +69,28 @@ __device__ __forceinline__ float column_of(const Geo &geo, const ViewParam &vp, 
 
 // Part of the z-profile of one (slice, column) pair: Z(kk) = sum_t hat(e_t - kk) * val(t)
 // for kk = kk0 .. kk0 + kKQ - 1, where row t of the pair's source has e_t = a0 + rowz * t
-// (eta relative to the pass's first z).  The NC = ceil(2 / rowz) candidates of each kk
-// start at the first row with e_t > kk - 1.
-template <int NC, typename Fetch>
-__device__ __forceinline__ void pair_profile(float a0, float rowz, int kk0, int t_lo, int t_hi, Fetch fetch,
-                                             float *zout, int zstride)
+// (eta relative to the pass's first z) and inv = 1 / rowz.  The NC = ceil(2 / rowz)
+// candidates of each kk start at the first row with e_t > kk - 1, clamped to
+// [t_lo, t_hi]; store(kk, Z) receives each entry.
+template <int NC, typename Fetch, typename Store>
+__device__ __forceinline__ void pair_profile(float a0, float rowz, float inv, int kk0, float t_lo, float t_hi,
+                                             Fetch fetch, Store store)
 {
-    const float inv = 1.0f / rowz;
+    const float am1 = -1.0f - a0;
 #pragma unroll
     for (int j = 0; j < kKQ; ++j) {
-        const float kk = (float)(kk0 + j);
-        const float rho = (kk - 1.0f - a0) * inv;   // e_t = kk - 1 at t = rho
-        int tf = (int)floorf(rho) + 1;
-        tf = min(max(tf, t_lo), t_hi);
-        float d = fmaf(rowz, (float)tf, a0 - kk);
+        const float rho = ((float)(kk0 + j) + am1) * inv;   // e_t = kk - 1 at t = rho
+        const float tf = __builtin_amdgcn_fmed3f(floorf(rho) + 1.0f, t_lo, t_hi);
+        const int t0 = (int)tf;
+        float d = fmaf(rowz, tf, a0 - (float)(kk0 + j));
         float s = 0.0f;
 #pragma unroll
         for (int t = 0; t < NC; ++t) {
             const float w = fmaxf(1.0f - fabsf(d), 0.0f);
-            s = fmaf(w, fetch(tf + t), s);
+            s = fmaf(w, fetch(t0 + t), s);
             d += rowz;
         }
-        zout[(kk0 + j) * zstride] = s;
+        store(kk0 + j, s);
     }
 }
 
@@ -107,6 +107,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
     __shared__ float xiq[NPM];                        // xi of the pair's column on its slice, minus q0
     __shared__ double ptau[NPM];                      // ray parameter there; 0 if xi misses the tile
     __shared__ short pcr[NPM];                        // the pair's column minus the class window's c0
+    __shared__ float pinv[NPM];                       // 1 / (row spacing in eta) of the pair
     __shared__ float win[kWinSize];                   // residual window, column-major, zero-padded rows
     __shared__ int colA[kTQ], colN[kTQ], pfx[kTQ];    // per slice: first column, count, first pair
 
@@ -201,7 +202,9 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 const double fm = (double)(mt0 + m);
                 const float xl = (float)(fma(fm, cp.xi1, cp.xi0) - (double)q0);
                 xiq[p] = xl;
-                ptau[p] = (xl > -1.0f && xl < (float)kTQ) ? fma(fm, cp.t1, cp.t0) : 0.0;
+                const double tau = (xl > -1.0f && xl < (float)kTQ) ? fma(fm, cp.t1, cp.t0) : 0.0;
+                ptau[p] = tau;
+                pinv[p] = tau != 0.0 ? 1.0f / (float)(tau * dvz) : 0.0f;
                 pcr[p] = (short)(c - c0);
             }
             // extremes of the ray parameter over the class's pairs: tau is monotone along
@@ -266,23 +269,25 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                     const double tau = ptau[pr];
                     if (tau == 0.0) continue;
                     const float rz = (float)(tau * dvz);
+                    const float inv = pinv[pr];
+                    auto store = [&](int kk, float zv) { Z[kk * NPM + pr] = zv; };
                     if (staged) {
                         const float a0 = (float)(geo.cz + tau * ((double)(r0 - kRowPad) - (double)geo.cv) * dvz -
                                                  (double)kb);
                         const float *__restrict__ wc = win + pcr[pr] * kWinStride;
-                        pair_profile<NC>(a0, rz, kq * kKQ, 0, kWinStride - NC, [&](int t) { return wc[t]; }, Z + pr,
-                                         NPM);
+                        pair_profile<NC>(a0, rz, inv, kq * kKQ, 0.0f, (float)(kWinStride - NC),
+                                         [&](int t) { return wc[t]; }, store);
                     } else {
                         // detector rows directly (rows outside [0, nv) do not exist)
                         const float a0 = (float)(geo.cz + tau * (0.0 - (double)geo.cv) * dvz - (double)kb);
                         const float *__restrict__ src = rwv + c0 + pcr[pr];
                         const int64_t nu = geo.nu;
-                        pair_profile<NC>(a0, rz, kq * kKQ, 0, max(0, geo.nv - NC),
+                        pair_profile<NC>(a0, rz, inv, kq * kKQ, 0.0f, (float)max(0, geo.nv - NC),
                                          [&](int t) {
                                              const float v = src[(int64_t)min(t, geo.nv - 1) * nu];
                                              return t < geo.nv ? v : 0.0f;
                                          },
-                                         Z + pr, NPM);
+                                         store);
                     }
                 }
                 __syncthreads();

@@ -114,7 +114,8 @@ hipError_t launch_prescale(const fbl_plan *p, const float *r, const ViewList &vl
 hipError_t launch_backproject(const fbl_plan *p, const float *rw, const ViewList &vl, int nb, int first,
                               bool accumulate, float *g, hipStream_t st);
 hipError_t launch_step(const fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo,
-                       double hi, void *xbar, int64_t *n_partials_used, hipStream_t st);
+                       double hi, bool stochastic, uint64_t key, void *xbar, int64_t *n_partials_used,
+                       hipStream_t st);
 
 size_t mlp_workspace_bytes(int64_t n);
 hipError_t launch_mlp_forward(const float *prm, const float *X, int64_t n, float *out, hipStream_t st);

@@ -226,6 +226,33 @@ ViewList chunk(const int32_t *views, int first, int nb)
     return vl;
 }
 
+int step_call(fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo, double hi,
+              bool stochastic, uint64_t key, void *xbar, double *red_dev, void *stream)
+{
+    if (!p) return fail(FBL_E_INVALID, "plan is NULL");
+    if (!x || !g || !xbar || !red_dev) return fail(FBL_E_INVALID, "x, g, xbar and red_dev must be non-NULL");
+    if (!aligned16(x) || !aligned16(g) || !aligned16(xbar) || !aligned8(red_dev))
+        return fail(FBL_E_INVALID, "arrays must be 16-byte aligned and red_dev 8-byte aligned");
+    if (xbar == x || (const void *)xbar == (const void *)g) return fail(FBL_E_INVALID, "xbar may not alias x or g");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(FBL_E_INVALID, "alpha must be finite and > 0");
+    if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(FBL_E_INVALID, "mu must be finite and >= 0");
+    if (!(lo >= 0.0) || !std::isfinite(lo) || !(hi >= lo))
+        return fail(FBL_E_INVALID, "bounds must satisfy 0 <= lo <= hi (lo finite)");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != p->device) return fail(FBL_E_INVALID, "the current device is not the plan's device");
+    hipStream_t st = (hipStream_t)stream;
+    int64_t nparts = 0;
+    e = timed(p, FBL_K_STEP, st,
+              [&] { return launch_step(p, x, g, alpha, mu, lo, hi, stochastic, key, xbar, &nparts, st); });
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    e = timed(p, FBL_K_FINALIZE, st, [&] { return launch_finalize_sum(p->d_partials, nparts, 3, 1.0, red_dev, st); });
+    if (e != hipSuccess) return hip_fail(e, "step reduction launch");
+    return ok();
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -505,29 +532,17 @@ int fb_lisa_backproject(fbl_plan *p, const float *r, const int32_t *views, int32
     return ok();
 }
 
+
 int fb_lisa_step(fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo, double hi, void *xbar,
                  double *red_dev, void *stream)
 {
-    if (!p) return fail(FBL_E_INVALID, "plan is NULL");
-    if (!x || !g || !xbar || !red_dev) return fail(FBL_E_INVALID, "x, g, xbar and red_dev must be non-NULL");
-    if (!aligned16(x) || !aligned16(g) || !aligned16(xbar) || !aligned8(red_dev))
-        return fail(FBL_E_INVALID, "arrays must be 16-byte aligned and red_dev 8-byte aligned");
-    if (xbar == x || (const void *)xbar == (const void *)g) return fail(FBL_E_INVALID, "xbar may not alias x or g");
-    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(FBL_E_INVALID, "alpha must be finite and > 0");
-    if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(FBL_E_INVALID, "mu must be finite and >= 0");
-    if (!(lo >= 0.0) || !std::isfinite(lo) || !(hi >= lo))
-        return fail(FBL_E_INVALID, "bounds must satisfy 0 <= lo <= hi (lo finite)");
-    int cur = -1;
-    hipError_t e = hipGetDevice(&cur);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    if (cur != p->device) return fail(FBL_E_INVALID, "the current device is not the plan's device");
-    hipStream_t st = (hipStream_t)stream;
-    int64_t nparts = 0;
-    e = timed(p, FBL_K_STEP, st, [&] { return launch_step(p, x, g, alpha, mu, lo, hi, xbar, &nparts, st); });
-    if (e != hipSuccess) return hip_fail(e, "step launch");
-    e = timed(p, FBL_K_FINALIZE, st, [&] { return launch_finalize_sum(p->d_partials, nparts, 3, 1.0, red_dev, st); });
-    if (e != hipSuccess) return hip_fail(e, "step reduction launch");
-    return ok();
+    return step_call(p, x, g, alpha, mu, lo, hi, false, 0, xbar, red_dev, stream);
+}
+
+int fb_lisa_step_sr(fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo, double hi,
+                    uint64_t key, void *xbar, double *red_dev, void *stream)
+{
+    return step_call(p, x, g, alpha, mu, lo, hi, true, key, xbar, red_dev, stream);
 }
 
 size_t fbl_mlp_workspace_bytes(int64_t n) { return n < 1 ? 0 : mlp_workspace_bytes(n); }

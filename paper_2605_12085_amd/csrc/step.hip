@@ -8,9 +8,10 @@ namespace {
 
 constexpr int kStepBlocks = 2048;   // 8 blocks per compute unit, grid-stride over the volume
 
-template <typename TV>
+// SR: round the trial point stochastically (counter-based, keyed) instead of to nearest.
+template <typename TV, bool SR>
 __global__ __launch_bounds__(256) void step_kernel(const TV *__restrict__ x, const float *__restrict__ g,
-                                                   double alpha, double amu, double lo, double hi,
+                                                   double alpha, double amu, double lo, double hi, uint64_t key,
                                                    TV *__restrict__ xbar, int64_t d, double *__restrict__ partials)
 {
     // the trial point is formed exactly as written, (x - alpha g) - alpha mu, without
@@ -23,7 +24,7 @@ __global__ __launch_bounds__(256) void step_kernel(const TV *__restrict__ x, con
         const double gv = (double)g[i];
         double v = (xv - alpha * gv) - amu;
         v = fmin(fmax(v, lo), hi);
-        const TV out = from_f64<TV>(v);
+        const TV out = SR ? round_stochastic<TV>(v, key, (uint64_t)i) : from_f64<TV>(v);
         xbar[i] = out;
         const double dl = (double)to_f32(out) - xv;
         s_inner += gv * dl;
@@ -49,27 +50,36 @@ int step_blocks(const fbl_plan *p)
     return (int)(need < kStepBlocks ? need : kStepBlocks);
 }
 
-template <typename TV>
+template <typename TV, bool SR>
 static hipError_t launch_step_t(const fbl_plan *p, const void *x, const float *g, double alpha, double amu,
-                                double lo, double hi, void *xbar, int blocks, hipStream_t st)
+                                double lo, double hi, uint64_t key, void *xbar, int blocks, hipStream_t st)
 {
     const int64_t d = (int64_t)p->geo.nx * p->geo.ny * p->geo.nz;
-    hipLaunchKernelGGL((step_kernel<TV>), dim3(blocks), dim3(256), 0, st, (const TV *)x, g, alpha, amu, lo, hi,
-                       (TV *)xbar, d, p->d_partials);
+    hipLaunchKernelGGL((step_kernel<TV, SR>), dim3(blocks), dim3(256), 0, st, (const TV *)x, g, alpha, amu, lo, hi,
+                       key, (TV *)xbar, d, p->d_partials);
     return hipGetLastError();
 }
 
+template <bool SR>
+static hipError_t launch_step_r(const fbl_plan *p, const void *x, const float *g, double alpha, double amu,
+                                double lo, double hi, uint64_t key, void *xbar, int blocks, hipStream_t st)
+{
+    switch (p->vol_dtype) {
+    case FBL_F32: return launch_step_t<float, SR>(p, x, g, alpha, amu, lo, hi, key, xbar, blocks, st);
+    case FBL_BF16: return launch_step_t<__hip_bfloat16, SR>(p, x, g, alpha, amu, lo, hi, key, xbar, blocks, st);
+    default: return launch_step_t<__half, SR>(p, x, g, alpha, amu, lo, hi, key, xbar, blocks, st);
+    }
+}
+
 hipError_t launch_step(const fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo,
-                       double hi, void *xbar, int64_t *n_partials_used, hipStream_t st)
+                       double hi, bool stochastic, uint64_t key, void *xbar, int64_t *n_partials_used,
+                       hipStream_t st)
 {
     const int blocks = step_blocks(p);
     *n_partials_used = blocks;
     const double amu = alpha * mu;
-    switch (p->vol_dtype) {
-    case FBL_F32: return launch_step_t<float>(p, x, g, alpha, amu, lo, hi, xbar, blocks, st);
-    case FBL_BF16: return launch_step_t<__hip_bfloat16>(p, x, g, alpha, amu, lo, hi, xbar, blocks, st);
-    default: return launch_step_t<__half>(p, x, g, alpha, amu, lo, hi, xbar, blocks, st);
-    }
+    return stochastic ? launch_step_r<true>(p, x, g, alpha, amu, lo, hi, key, xbar, blocks, st)
+                      : launch_step_r<false>(p, x, g, alpha, amu, lo, hi, key, xbar, blocks, st);
 }
 
 }  // namespace fbl

@@ -86,7 +86,7 @@ class FBLisa:
                  mu: float = 0.0, lo: float = 0.0, hi: float = math.inf, C: Optional[float] = None,
                  n_max: Optional[int] = None, eps: Callable[[int], float] = eps_power, j_max: int = 50,
                  x0: Optional[torch.Tensor] = None, vol_dtype: str = "f32", proj_dtype: Optional[str] = None,
-                 plan: Optional[Plan] = None):
+                 plan: Optional[Plan] = None, sr_seed: Optional[int] = None):
         self.geom = geom
         self.n = int(geom.n_views)
         self.n0, self.epochs = int(n0), int(epochs)
@@ -110,6 +110,11 @@ class FBLisa:
         # device scalars: [0] f(x), [2] f(xbar), [4] <g, d>, [5] ||d||^2, [6] ||g||^2
         self.scal = torch.zeros(8, dtype=torch.float64, device=dev)
         self.host = torch.zeros(8, dtype=torch.float64).pin_memory()
+        # stochastic rounding of the stored iterates: trial j of iteration k uses the key
+        # (sr_seed << 32) + (k << 6) + j (j < 64 since at most 51 trials run)
+        if sr_seed is not None and self.j_max > 63:
+            raise ValueError("stochastic rounding keys allow at most 64 trials per iteration (j_max <= 63)")
+        self.sr_seed = sr_seed
         self.k = 0
         self.epoch = 0
         self.history: List[Iteration] = []
@@ -138,7 +143,9 @@ class FBLisa:
         trials: List[Trial] = []
         stream = torch.cuda.current_stream()
         for j in range(self.j_max + 1):
-            fb_lisa_step(plan, self.x, self.g, alpha, self.mu, self.lo, self.hi, self.xbar, self.scal[4:7])
+            key = None if self.sr_seed is None else (((int(self.sr_seed) << 32) + (self.k << 6) + j)
+                                                     & 0xFFFFFFFFFFFFFFFF)
+            fb_lisa_step(plan, self.x, self.g, alpha, self.mu, self.lo, self.hi, self.xbar, self.scal[4:7], key=key)
             fb_lisa_forward(plan, self.xbar, v, self.b, rbar, self.scal[2:3], f_scale)
             self.host.copy_(self.scal, non_blocking=True)
             stream.synchronize()

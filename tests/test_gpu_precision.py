@@ -195,3 +195,56 @@ def test_16bit_iterates_replay_and_error_against_fp64(fbl, orc, st, capsys):
               % (st, re_st, re_32, orc.rmse(xf, xt), orc.rmse(x32, xt), orc.rmse(x64, xt)), flush=True)
     assert re_32 <= 1e-3
     assert re_st <= 4 * U[st]
+
+
+@pytest.mark.parametrize("st", ["bf16", "f16", "f32"])
+def test_step_stochastic_rounding_matches_oracle(fbl, orc, st):
+    # the rounding decision depends only on the FP64 trial value, the key and the voxel
+    # index, so the GPU's stored trial point equals the oracle's replay of the same draw
+    import torch
+    g = ODD
+    rng = np.random.default_rng(23)
+    xs = orc.round_storage(rng.uniform(0, 0.03, g.vol_shape), st)
+    xs[rng.random(g.vol_shape) < 0.2] = 0.0
+    grad = (rng.standard_normal(g.vol_shape) * 3.0).astype(np.float32)
+    with fbl.Plan(g, vol_dtype=st) as plan:
+        outs = []
+        for key, (alpha, mu, lo, hi) in ((0x1234, (1e-3, 0.0, 0.0, math.inf)), (2 ** 63 + 5, (2.5e-3, 0.7, 0.0, 0.03))):
+            red = torch.zeros(3, dtype=torch.float64, device="cuda")
+            xb, red = fbl.fb_lisa_step(plan, _dev(xs, st), torch.from_numpy(grad).cuda(), alpha, mu, lo, hi,
+                                       red=red, key=key)
+            xb = xb.to(torch.float64).cpu().numpy()
+            red = red.cpu().numpy()
+            xr, inner, sq, gg = orc.prox_step(xs, grad, alpha, mu, lo, hi, storage=st, key=key)
+            assert np.mean(xb == xr) > 0.999
+            assert np.all(np.abs(xb - xr) <= _storage_ulp(xr, st))
+            assert red[0] == pytest.approx(inner, rel=1e-9)
+            assert red[1] == pytest.approx(sq, rel=1e-9)
+            outs.append(xb)
+        # stochastic, not nearest: some values differ from the nearest rounding
+        xn, _ = fbl.fb_lisa_step(plan, _dev(xs, st), torch.from_numpy(grad).cuda(), 1e-3, 0.0, 0.0, math.inf)
+        assert not np.array_equal(outs[0], xn.to(torch.float64).cpu().numpy())
+
+
+def test_bf16_stochastic_iterates_replay(fbl, orc, capsys):
+    """BF16 iterates with stochastic rounding: the GPU replays the oracle's BF16 run with
+    the same keys (trial j of iteration k uses (seed << 32) + (k << 6) + j)."""
+    import torch
+    g, xt, b32, perms = _loop_problem()
+    epochs, n0, seed = 2, 4, 99
+    b64 = b32.astype(np.float64)
+    x64, _ = orc.fblisa(g, b64, epochs=epochs, n0=n0, perms=perms)
+    xs_o = []
+    xo, rec = orc.fblisa(g, b64, epochs=epochs, n0=n0, perms=perms, storage="bf16", sr_seed=seed,
+                         callback=lambda k, x, r: xs_o.append(x.copy()))
+    decisions = [[t.accepted for t in r.trials] for r in rec]
+    bd = torch.from_numpy(b32).cuda()
+    xs_g = []
+    run = fbl.FBLisa(g, bd, n0=n0, epochs=epochs, vol_dtype="bf16", sr_seed=seed)
+    run.run(perms, decisions=decisions, callback=lambda s, it: xs_g.append(s.x.to(torch.float64).cpu().numpy()))
+    for k, (a, b) in enumerate(zip(xs_g, xs_o)):
+        assert np.linalg.norm(a - b) <= U["bf16"] * np.linalg.norm(b), k
+    with capsys.disabled():
+        print("\nbf16 iterates, stochastic rounding: RE vs FP64 run %.3e; RMSE vs phantom %.4e (FP64 %.4e)"
+              % (orc.relative_error(xs_g[-1], x64), orc.rmse(xs_g[-1], xt), orc.rmse(x64, xt)), flush=True)
+    assert orc.relative_error(xs_g[-1], x64) <= 4 * U["bf16"]

@@ -78,3 +78,44 @@ def test_prox_step_with_storage(orc):
         exact = np.clip(x - 1e-3 * grad - 1e-3 * 0.5, 0.0, 0.03)
         ulp = 2.0 ** -8 if st == "bf16" else 2.0 ** -11   # unit roundoff
         assert np.all(np.abs(xb - exact) <= ulp * np.abs(exact) + 2.0 ** -24)
+
+
+def test_splitmix64_published_outputs(orc):
+    # the first outputs of SplitMix64 seeded with 0, as published with the generator
+    z = orc.splitmix64(0, [0, 1, 2])
+    assert [int(v) for v in z] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    # a stream continues across counters: output c+1 of seed k equals output c of seed k + gamma
+    assert int(orc.splitmix64(5, [7])[0]) == int(orc.splitmix64(5 + 0x9E3779B97F4A7C15, [6])[0])
+
+
+def test_stochastic_rounding_probability_and_bias(orc):
+    n = 200000
+    for st, q in (("bf16", 2.0 ** -7), ("f16", 2.0 ** -10), ("f32", 2.0 ** -23)):
+        for frac in (0.25, 0.5, 0.9):
+            v = np.full(n, 1.0 + frac * q)
+            r = orc.round_stochastic(v, st, key=77)
+            assert set(np.unique(r)) <= {1.0, 1.0 + q}
+            up = np.mean(r > 1.0)
+            assert abs(up - frac) < 5 * math.sqrt(frac * (1 - frac) / n), (st, frac, up)
+    # unbiased on average over keys, and exact where representable
+    rng = np.random.default_rng(3)
+    v = rng.uniform(0.001, 0.03, 1000)
+    mean = np.mean([orc.round_stochastic(v, "bf16", key=k) for k in range(400)], axis=0)
+    q = np.ldexp(1.0, np.frexp(v)[1] - 8)
+    assert np.all(np.abs(mean - v) < 5 * 0.5 * q / math.sqrt(400))
+    rep = orc.round_bf16(v)
+    assert np.array_equal(orc.round_stochastic(rep, "bf16", key=9), rep)
+    # the result is one of the two neighbours and depends only on (value, key, index)
+    r1 = orc.round_stochastic(v, "bf16", key=11)
+    assert np.array_equal(r1, orc.round_stochastic(v, "bf16", key=11))
+    assert not np.array_equal(r1, orc.round_stochastic(v, "bf16", key=12))
+    lo = np.floor(v / q) * q
+    assert np.all((r1 == lo) | (r1 == lo + q))
+
+
+def test_stochastic_rounding_subnormal_quantum(orc):
+    # below the smallest normal FP16 number 2^-14 the quantum stays 2^-24
+    v = np.full(100000, 3.25 * 2.0 ** -24)
+    r = orc.round_stochastic(v, "f16", key=5)
+    assert set(np.unique(r)) == {3.0 * 2.0 ** -24, 4.0 * 2.0 ** -24}
+    assert abs(np.mean(r == 4.0 * 2.0 ** -24) - 0.25) < 0.01
