@@ -103,6 +103,9 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
     constexpr int NPM = kTQ * WP;                     // pair slots: 16 slices x WP columns
     constexpr int kWinCols = WP + kWinExtra;          // column union of the 16 slices
     constexpr int kWinSize = kWinCols * kWinStride;
+    constexpr int kColSweeps = (kWinCols + 63) / 64;        // window columns per lane
+    constexpr int kRowIters = (kWinStride + 3) / 4;         // window rows per wave
+    constexpr int kPairIters = (NPM + kThreads - 1) / kThreads;
     __shared__ float Z[kKH * NPM];                    // Z[k][pair]: half-pass z-profile of each pair
     __shared__ float xiq[NPM];                        // xi of the pair's column on its slice, minus q0
     __shared__ double ptau[NPM];                      // ray parameter there; 0 if xi misses the tile
@@ -193,20 +196,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 NP += n;
             }
             if (c1 < 0) continue;   // uniform across the block
-            // 2. pair geometry: xi for the voxel gather, the ray parameter for the profile
-            for (int p = tid; p < NP; p += kThreads) {
-                int m = 0, end = colN[0];
-                while (p >= end) end += colN[++m];   // p < NP, so m stays below kTQ
-                const int c = colA[m] + (p - (end - colN[m]));
-                const ColParam cp = cols[c];
-                const double fm = (double)(mt0 + m);
-                const float xl = (float)(fma(fm, cp.xi1, cp.xi0) - (double)q0);
-                xiq[p] = xl;
-                const double tau = (xl > -1.0f && xl < (float)kTQ) ? fma(fm, cp.t1, cp.t0) : 0.0;
-                ptau[p] = tau;
-                pinv[p] = tau != 0.0 ? 1.0f / (float)(tau * dvz) : 0.0f;
-                pcr[p] = (short)(c - c0);
-            }
+            const int nC = c1 - c0 + 1;
             // extremes of the ray parameter over the class's pairs: tau is monotone along
             // a detector row (inversely proportional to the column's D_a, which is affine
             // in the column) and affine in the slice, so they sit at the corner (first/last
@@ -221,47 +211,97 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 imin = 1.0f / (float)(fmax(fmax(t00, t01), fmax(t10, t11)) * dvz);
                 imax = 1.0f / (float)(fmin(fmin(t00, t01), fmin(t10, t11)) * dvz);
             }
-            const int nC = c1 - c0 + 1;
-            __syncthreads();   // pair tables complete
+            // per half: detector rows that can reach z in (kb - 1, kb + kKH), kb = k0 + h kKH
+            int r0h[2], nRh[2];
+            bool stg[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int kb = k0 + h * kKH;
+                const float e0 = (float)((double)(kb - 1) - geo.cz), e1 = (float)((double)(kb + kKH) - geo.cz);
+                const float a = e0 * imin, b = e0 * imax, c = e1 * imin, d = e1 * imax;
+                const float rlo = fminf(fminf(a, b), fminf(c, d)) + geo.cv;
+                const float rhi = fmaxf(fmaxf(a, b), fmaxf(c, d)) + geo.cv;
+                r0h[h] = max(0, (int)floorf(rlo) - 1);
+                nRh[h] = min(geo.nv - 1, (int)ceilf(rhi) + 1) - r0h[h] + 1;
+                stg[h] = nRh[h] > 0 && nRh[h] <= kWinRows && nC <= kWinCols;
+            }
+            // Every global load of the class is issued before the first use of any: the
+            // pairs' column parameters and both halves' residual windows.  Window row t
+            // holds detector row r0 - kRowPad + t (zero outside [kRowPad, kRowPad + nR));
+            // lanes run along columns (contiguous in memory), waves along rows.  The second
+            // half's window stays in registers until the first half's profiles are done.
+            float wv[2][kColSweeps][kRowIters];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int cs = 0; cs < kColSweeps; ++cs) {
+                    const int col = lane + 64 * cs;
+#pragma unroll
+                    for (int i = 0; i < kRowIters; ++i) {
+                        const int t = wave + 4 * i;
+                        const bool ld = stg[h] && col < nC && t >= kRowPad && t < kRowPad + nRh[h];
+                        wv[h][cs][i] = ld ? rwv[(int64_t)(r0h[h] - kRowPad + t) * geo.nu + c0 + col] : 0.0f;
+                    }
+                }
+            ColParam pc[kPairIters];
+            int pm[kPairIters], pcol[kPairIters];
+#pragma unroll
+            for (int i = 0; i < kPairIters; ++i) {
+                const int p = tid + i * kThreads;
+                pm[i] = -1;
+                pcol[i] = 0;
+                if (p < NP) {
+                    int m = 0, end = colN[0];
+                    while (p >= end) end += colN[++m];   // p < NP, so m stays below kTQ
+                    pm[i] = m;
+                    pcol[i] = colA[m] + (p - (end - colN[m]));
+                    pc[i] = cols[pcol[i]];
+                }
+            }
+            // 2. pair geometry: xi for the voxel gather, the ray parameter for the profile
+#pragma unroll
+            for (int i = 0; i < kPairIters; ++i) {
+                const int p = tid + i * kThreads;
+                if (pm[i] >= 0) {
+                    const int m = pm[i];
+                    const ColParam &cp = pc[i];
+                    const double fm = (double)(mt0 + m);
+                    const float xl = (float)(fma(fm, cp.xi1, cp.xi0) - (double)q0);
+                    xiq[p] = xl;
+                    const double tau = (xl > -1.0f && xl < (float)kTQ) ? fma(fm, cp.t1, cp.t0) : 0.0;
+                    ptau[p] = tau;
+                    pinv[p] = tau != 0.0 ? 1.0f / (float)(tau * dvz) : 0.0f;
+                    pcr[p] = (short)(pcol[i] - c0);
+                }
+            }
+            auto store_window = [&](int h) {
+#pragma unroll
+                for (int cs = 0; cs < kColSweeps; ++cs) {
+                    const int col = lane + 64 * cs;
+                    if (col < nC) {
+#pragma unroll
+                        for (int i = 0; i < kRowIters; ++i) {
+                            const int t = wave + 4 * i;
+                            if (t < kWinStride) win[col * kWinStride + t] = h == 0 ? wv[0][cs][i] : wv[1][cs][i];
+                        }
+                    }
+                }
+            };
+            if (stg[0]) store_window(0);
+            __syncthreads();   // pair tables and the first half's window complete
 
             auto half_pass = [&](auto hc) {
                 constexpr int h = decltype(hc)::value;
                 const int kb = k0 + h * kKH;   // first z of this half
-                // detector rows that can reach z in (kb - 1, kb + kKH)
-                int r0, nR;
-                {
-                    const float e0 = (float)((double)(kb - 1) - geo.cz), e1 = (float)((double)(kb + kKH) - geo.cz);
-                    const float a = e0 * imin, b = e0 * imax, c = e1 * imin, d = e1 * imax;
-                    const float rlo = fminf(fminf(a, b), fminf(c, d)) + geo.cv;
-                    const float rhi = fmaxf(fmaxf(a, b), fmaxf(c, d)) + geo.cv;
-                    r0 = max(0, (int)floorf(rlo) - 1);
-                    nR = min(geo.nv - 1, (int)ceilf(rhi) + 1) - r0 + 1;
-                }
+                const int r0 = r0h[h], nR = nRh[h];
                 if (nR <= 0) return;   // uniform across the block
-                const bool staged = nR <= kWinRows && nC <= kWinCols;
-                if (staged) {
-                    // window row t holds detector row r0 - kRowPad + t; rows outside
-                    // [kRowPad, kRowPad + nR) are zero.  Lanes run along columns (contiguous
-                    // in memory), waves along rows; four rows' loads are issued together.
-                    for (int col = lane; col < nC; col += 64) {
-                        const float *__restrict__ src = rwv + c0 + col;   // detector row 0 of the column
-                        float *__restrict__ dst = win + col * kWinStride;
-                        for (int t = wave; t < kWinStride; t += 16) {
-                            float v[4];
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const int tu = t + 4 * u;
-                                v[u] = (tu >= kRowPad && tu < kRowPad + nR)
-                                           ? src[(int64_t)(r0 - kRowPad + tu) * geo.nu]
-                                           : 0.0f;
-                            }
-#pragma unroll
-                            for (int u = 0; u < 4; ++u)
-                                if (t + 4 * u < kWinStride) dst[t + 4 * u] = v[u];
-                        }
-                    }
+                const bool staged = stg[h];
+                if (h == 1) {
+                    // the first half's profiles, the window's only readers, ended at the
+                    // barrier before its gather; this barrier also ends that gather (Z)
+                    if (staged) store_window(1);
+                    __syncthreads();
                 }
-                __syncthreads();   // window staged; the previous half's gather of Z is done
                 // 3. profiles: item (pair, quarter of the half's z-range)
                 for (int it = tid; it < (kKH / kKQ) * NP; it += kThreads) {
                     int kq = 0, pr = it;
