@@ -315,8 +315,14 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                         const float a0 = (float)(geo.cz + tau * ((double)(r0 - kRowPad) - (double)geo.cv) * dvz -
                                                  (double)kb);
                         const float *__restrict__ wc = win + pcr[pr] * kWinStride;
-                        pair_profile<NC>(a0, rz, inv, kq * kKQ, 0.0f, (float)(kWinStride - NC),
-                                         [&](int t) { return wc[t]; }, store);
+                        auto fetch = [&](int t) { return wc[t]; };
+                        // NC covers the finest row spacing of the plan; where every lane of the
+                        // wave has spacing >= 2/(NC-1) (plus a rounding margin), NC-1 do
+                        constexpr int NCL = NC > 3 ? NC - 1 : NC;
+                        if (NCL < NC && __all(rz * (float)NCL >= 2.001f))
+                            pair_profile<NCL>(a0, rz, inv, kq * kKQ, 0.0f, (float)(kWinStride - NCL), fetch, store);
+                        else
+                            pair_profile<NC>(a0, rz, inv, kq * kKQ, 0.0f, (float)(kWinStride - NC), fetch, store);
                     } else {
                         // detector rows directly (rows outside [0, nv) do not exist)
                         const float a0 = (float)(geo.cz + tau * (0.0 - (double)geo.cv) * dvz - (double)kb);
