@@ -36,6 +36,7 @@ constexpr int kTQ = 16;        // tile extent along x and along y (and slices pe
 constexpr int kTK = 16;        // tile extent along z (voxels per thread)
 constexpr int kKH = 8;         // z-entries per half pass
 constexpr int kKQ = 4;         // z-entries per profile work item
+static_assert(kKH == 2 * kKQ, "a half pass has two profile items per pair");
 constexpr int kThreads = 256;
 constexpr int kRowPad = 8;     // zero rows above and below the staged residual window
 constexpr int kWinRows = 32;   // staged rows per column (longer spans read global memory)
@@ -225,24 +226,39 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 nRh[h] = min(geo.nv - 1, (int)ceilf(rhi) + 1) - r0h[h] + 1;
                 stg[h] = nRh[h] > 0 && nRh[h] <= kWinRows && nC <= kWinCols;
             }
-            // Every global load of the class is issued before the first use of any: the
-            // pairs' column parameters and both halves' residual windows.  Window row t
-            // holds detector row r0 - kRowPad + t (zero outside [kRowPad, kRowPad + nR));
-            // lanes run along columns (contiguous in memory), waves along rows.  The second
-            // half's window stays in registers until the first half's profiles are done.
-            float wv[2][kColSweeps][kRowIters];
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
+            // The pairs' column parameters and the first half's residual window are loaded
+            // together, before either is used.  Window row t holds detector row
+            // r0 - kRowPad + t (zero outside [kRowPad, kRowPad + nR)); lanes run along
+            // columns (contiguous in memory), waves along rows.  The second half's window is
+            // loaded when that half starts (holding it in registers across the first half
+            // would cost occupancy).
+            float wv[kColSweeps][kRowIters];
+            auto load_window = [&](int h) {
 #pragma unroll
                 for (int cs = 0; cs < kColSweeps; ++cs) {
                     const int col = lane + 64 * cs;
 #pragma unroll
                     for (int i = 0; i < kRowIters; ++i) {
                         const int t = wave + 4 * i;
-                        const bool ld = stg[h] && col < nC && t >= kRowPad && t < kRowPad + nRh[h];
-                        wv[h][cs][i] = ld ? rwv[(int64_t)(r0h[h] - kRowPad + t) * geo.nu + c0 + col] : 0.0f;
+                        const bool ld = col < nC && t >= kRowPad && t < kRowPad + nRh[h];
+                        wv[cs][i] = ld ? rwv[(int64_t)(r0h[h] - kRowPad + t) * geo.nu + c0 + col] : 0.0f;
                     }
                 }
+            };
+            auto store_window = [&]() {
+#pragma unroll
+                for (int cs = 0; cs < kColSweeps; ++cs) {
+                    const int col = lane + 64 * cs;
+                    if (col < nC) {
+#pragma unroll
+                        for (int i = 0; i < kRowIters; ++i) {
+                            const int t = wave + 4 * i;
+                            if (t < kWinStride) win[col * kWinStride + t] = wv[cs][i];
+                        }
+                    }
+                }
+            };
+            if (stg[0]) load_window(0);
             ColParam pc[kPairIters];
             int pm[kPairIters], pcol[kPairIters];
 #pragma unroll
@@ -274,20 +290,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                     pcr[p] = (short)(pcol[i] - c0);
                 }
             }
-            auto store_window = [&](int h) {
-#pragma unroll
-                for (int cs = 0; cs < kColSweeps; ++cs) {
-                    const int col = lane + 64 * cs;
-                    if (col < nC) {
-#pragma unroll
-                        for (int i = 0; i < kRowIters; ++i) {
-                            const int t = wave + 4 * i;
-                            if (t < kWinStride) win[col * kWinStride + t] = h == 0 ? wv[0][cs][i] : wv[1][cs][i];
-                        }
-                    }
-                }
-            };
-            if (stg[0]) store_window(0);
+            if (stg[0]) store_window();
             __syncthreads();   // pair tables and the first half's window complete
 
             auto half_pass = [&](auto hc) {
@@ -299,41 +302,71 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 if (h == 1) {
                     // the first half's profiles, the window's only readers, ended at the
                     // barrier before its gather; this barrier also ends that gather (Z)
-                    if (staged) store_window(1);
+                    if (staged) {
+                        load_window(1);
+                        store_window();
+                    }
                     __syncthreads();
                 }
                 // 3. profiles: item (pair, quarter of the half's z-range)
-                for (int it = tid; it < (kKH / kKQ) * NP; it += kThreads) {
-                    int kq = 0, pr = it;
-                    while (pr >= NP) { pr -= NP; ++kq; }
-                    const double tau = ptau[pr];
-                    if (tau == 0.0) continue;
-                    const float rz = (float)(tau * dvz);
-                    const float inv = pinv[pr];
-                    auto store = [&](int kk, float zv) { Z[kk * NPM + pr] = zv; };
-                    if (staged) {
-                        const float a0 = (float)(geo.cz + tau * ((double)(r0 - kRowPad) - (double)geo.cv) * dvz -
-                                                 (double)kb);
-                        const float *__restrict__ wc = win + pcr[pr] * kWinStride;
-                        auto fetch = [&](int t) { return wc[t]; };
-                        // NC covers the finest row spacing of the plan; where every lane of the
-                        // wave has spacing >= 2/(NC-1) (plus a rounding margin), NC-1 do
-                        constexpr int NCL = NC > 3 ? NC - 1 : NC;
-                        if (NCL < NC && __all(rz * (float)NCL >= 2.001f))
-                            pair_profile<NCL>(a0, rz, inv, kq * kKQ, 0.0f, (float)(kWinStride - NCL), fetch, store);
-                        else
-                            pair_profile<NC>(a0, rz, inv, kq * kKQ, 0.0f, (float)(kWinStride - NC), fetch, store);
-                    } else {
+                const int nItems = (kKH / kKQ) * NP;
+                const double cz_kb = geo.cz - (double)kb;
+                if (staged) {
+                    // Two items per lane and round, without branches: an item that needs no
+                    // profile (the pair misses the tile, or the index runs past the end)
+                    // computes on harmless stand-in values and skips its stores, so the two
+                    // items' dependent LDS reads and arithmetic overlap.
+                    const double wrow0 = (double)(r0 - kRowPad) - (double)geo.cv;   // eta slope units of window row 0
+                    for (int it0 = tid; it0 < nItems; it0 += 2 * kThreads) {
+                        float a0[2], rz[2], inv[2], zv[2][kKQ];
+                        int wofs[2], pr[2], kk0[2];
+                        bool ok[2];
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            const int it = it0 + u * kThreads;
+                            int p = it < nItems ? it : 0, kq = 0;
+                            if (p >= NP) { p -= NP; kq = 1; }
+                            const double tau = ptau[p];
+                            ok[u] = it < nItems && tau != 0.0;
+                            const double B = ok[u] ? tau * dvz : 1.0;   // row spacing in eta
+                            rz[u] = (float)B;
+                            inv[u] = ok[u] ? pinv[p] : 1.0f;
+                            a0[u] = ok[u] ? (float)fma(B, wrow0, cz_kb) : 0.0f;
+                            wofs[u] = pcr[p] * kWinStride;
+                            pr[u] = p;
+                            kk0[u] = kq * kKQ;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            const float *__restrict__ wc = win + wofs[u];
+                            pair_profile<NC>(a0[u], rz[u], inv[u], kk0[u], 0.0f, (float)(kWinStride - NC),
+                                             [&](int t) { return wc[t]; },
+                                             [&](int kk, float z) { zv[u][kk - kk0[u]] = z; });
+                        }
+#pragma unroll
+                        for (int u = 0; u < 2; ++u)
+                            if (ok[u]) {
+#pragma unroll
+                                for (int j = 0; j < kKQ; ++j) Z[(kk0[u] + j) * NPM + pr[u]] = zv[u][j];
+                            }
+                    }
+                } else {
+                    for (int it = tid; it < nItems; it += kThreads) {
+                        int pr = it, kq = 0;
+                        if (pr >= NP) { pr -= NP; kq = 1; }
+                        const double tau = ptau[pr];
+                        if (tau == 0.0) continue;
+                        const double B = tau * dvz;
                         // detector rows directly (rows outside [0, nv) do not exist)
-                        const float a0 = (float)(geo.cz + tau * (0.0 - (double)geo.cv) * dvz - (double)kb);
+                        const float a0 = (float)fma(B, -(double)geo.cv, cz_kb);
                         const float *__restrict__ src = rwv + c0 + pcr[pr];
                         const int64_t nu = geo.nu;
-                        pair_profile<NC>(a0, rz, inv, kq * kKQ, 0.0f, (float)max(0, geo.nv - NC),
+                        pair_profile<NC>(a0, (float)B, pinv[pr], kq * kKQ, 0.0f, (float)max(0, geo.nv - NC),
                                          [&](int t) {
                                              const float v = src[(int64_t)min(t, geo.nv - 1) * nu];
                                              return t < geo.nv ? v : 0.0f;
                                          },
-                                         store);
+                                         [&](int kk, float z) { Z[kk * NPM + pr] = z; });
                     }
                 }
                 __syncthreads();
