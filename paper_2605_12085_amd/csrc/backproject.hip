@@ -109,9 +109,10 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
     constexpr int kPairIters = (NPM + kThreads - 1) / kThreads;
     __shared__ float Z[kKH * NPM];                    // Z[k][pair]: half-pass z-profile of each pair
     __shared__ float xiq[NPM];                        // xi of the pair's column on its slice, minus q0
-    __shared__ double ptau[NPM];                      // ray parameter there; 0 if xi misses the tile
+    __shared__ float prz[NPM];                        // row spacing in eta there; 0 if xi misses the tile
+    __shared__ float pa0[2][NPM];                     // per half: eta of the pair's source row 0, minus the
+                                                      // half's first z (window row 0 if staged, else detector row 0)
     __shared__ short pcr[NPM];                        // the pair's column minus the class window's c0
-    __shared__ float pinv[NPM];                       // 1 / (row spacing in eta) of the pair
     __shared__ float win[kWinSize];                   // residual window, column-major, zero-padded rows
     __shared__ int colA[kTQ], colN[kTQ], pfx[kTQ];    // per slice: first column, count, first pair
 
@@ -284,9 +285,14 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                     const double fm = (double)(mt0 + m);
                     const float xl = (float)(fma(fm, cp.xi1, cp.xi0) - (double)q0);
                     xiq[p] = xl;
-                    const double tau = (xl > -1.0f && xl < (float)kTQ) ? fma(fm, cp.t1, cp.t0) : 0.0;
-                    ptau[p] = tau;
-                    pinv[p] = tau != 0.0 ? 1.0f / (float)(tau * dvz) : 0.0f;
+                    const bool in = xl > -1.0f && xl < (float)kTQ;
+                    const double B = fma(fm, cp.t1, cp.t0) * dvz;   // tau dv/hz: eta per detector row
+                    prz[p] = in ? (float)B : 0.0f;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const double row0 = stg[h] ? (double)(r0h[h] - kRowPad) : 0.0;
+                        pa0[h][p] = (float)fma(B, row0 - (double)geo.cv, geo.cz - (double)(k0 + h * kKH));
+                    }
                     pcr[p] = (short)(pcol[i] - c0);
                 }
             }
@@ -295,8 +301,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
 
             auto half_pass = [&](auto hc) {
                 constexpr int h = decltype(hc)::value;
-                const int kb = k0 + h * kKH;   // first z of this half
-                const int r0 = r0h[h], nR = nRh[h];
+                const int nR = nRh[h];
                 if (nR <= 0) return;   // uniform across the block
                 const bool staged = stg[h];
                 if (h == 1) {
@@ -310,13 +315,11 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 }
                 // 3. profiles: item (pair, quarter of the half's z-range)
                 const int nItems = (kKH / kKQ) * NP;
-                const double cz_kb = geo.cz - (double)kb;
                 if (staged) {
                     // Two items per lane and round, without branches: an item that needs no
                     // profile (the pair misses the tile, or the index runs past the end)
                     // computes on harmless stand-in values and skips its stores, so the two
                     // items' dependent LDS reads and arithmetic overlap.
-                    const double wrow0 = (double)(r0 - kRowPad) - (double)geo.cv;   // eta slope units of window row 0
                     for (int it0 = tid; it0 < nItems; it0 += 2 * kThreads) {
                         float a0[2], rz[2], inv[2], zv[2][kKQ];
                         int wofs[2], pr[2], kk0[2];
@@ -326,12 +329,11 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                             const int it = it0 + u * kThreads;
                             int p = it < nItems ? it : 0, kq = 0;
                             if (p >= NP) { p -= NP; kq = 1; }
-                            const double tau = ptau[p];
-                            ok[u] = it < nItems && tau != 0.0;
-                            const double B = ok[u] ? tau * dvz : 1.0;   // row spacing in eta
-                            rz[u] = (float)B;
-                            inv[u] = ok[u] ? pinv[p] : 1.0f;
-                            a0[u] = ok[u] ? (float)fma(B, wrow0, cz_kb) : 0.0f;
+                            const float r = prz[p];
+                            ok[u] = it < nItems && r != 0.0f;
+                            rz[u] = ok[u] ? r : 1.0f;
+                            inv[u] = 1.0f / rz[u];
+                            a0[u] = ok[u] ? pa0[h][p] : 0.0f;
                             wofs[u] = pcr[p] * kWinStride;
                             pr[u] = p;
                             kk0[u] = kq * kKQ;
@@ -354,14 +356,12 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                     for (int it = tid; it < nItems; it += kThreads) {
                         int pr = it, kq = 0;
                         if (pr >= NP) { pr -= NP; kq = 1; }
-                        const double tau = ptau[pr];
-                        if (tau == 0.0) continue;
-                        const double B = tau * dvz;
+                        const float rz = prz[pr];
+                        if (rz == 0.0f) continue;
                         // detector rows directly (rows outside [0, nv) do not exist)
-                        const float a0 = (float)fma(B, -(double)geo.cv, cz_kb);
                         const float *__restrict__ src = rwv + c0 + pcr[pr];
                         const int64_t nu = geo.nu;
-                        pair_profile<NC>(a0, (float)B, pinv[pr], kq * kKQ, 0.0f, (float)max(0, geo.nv - NC),
+                        pair_profile<NC>(pa0[h][pr], rz, 1.0f / rz, kq * kKQ, 0.0f, (float)max(0, geo.nv - NC),
                                          [&](int t) {
                                              const float v = src[(int64_t)min(t, geo.nv - 1) * nu];
                                              return t < geo.nv ? v : 0.0f;
