@@ -186,17 +186,25 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
             __syncthreads();
             // the class window's columns [c0, c1] (union of the slices' ranges), the pair
             // count and each slice's first pair (every thread forms them alike)
-            int c0 = INT_MAX, c1 = -1, NP = 0;
+            // The slice table is read into registers first (no LDS write in between, so the
+            // reads are not serialised), then reduced.
+            int sA[kTQ], sN[kTQ];
 #pragma unroll
             for (int m = 0; m < kTQ; ++m) {
-                const int n = colN[m];
-                if (tid == m) pfx[m] = NP;
-                if (n > 0) {
-                    c0 = min(c0, colA[m]);
-                    c1 = max(c1, colA[m] + n - 1);
-                }
-                NP += n;
+                sA[m] = colA[m];
+                sN[m] = colN[m];
             }
+            int c0 = INT_MAX, c1 = -1, NP = 0, myfirst = 0;
+#pragma unroll
+            for (int m = 0; m < kTQ; ++m) {
+                if (tid == m) myfirst = NP;
+                if (sN[m] > 0) {
+                    c0 = min(c0, sA[m]);
+                    c1 = max(c1, sA[m] + sN[m] - 1);
+                }
+                NP += sN[m];
+            }
+            if (tid < kTQ) pfx[tid] = myfirst;   // read after the barrier that ends the set-up
             if (c1 < 0) continue;   // uniform across the block
             const int nC = c1 - c0 + 1;
             // extremes of the ray parameter over the class's pairs: tau is monotone along
@@ -268,10 +276,16 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 pm[i] = -1;
                 pcol[i] = 0;
                 if (p < NP) {
-                    int m = 0, end = colN[0];
-                    while (p >= end) end += colN[++m];   // p < NP, so m stays below kTQ
-                    pm[i] = m;
-                    pcol[i] = colA[m] + (p - (end - colN[m]));
+                    // the slice whose pairs [start, start + n) hold p, from the registers
+                    int start = 0;
+#pragma unroll
+                    for (int m = 0; m < kTQ; ++m) {
+                        if (p >= start && p < start + sN[m]) {
+                            pm[i] = m;
+                            pcol[i] = sA[m] + (p - start);
+                        }
+                        start += sN[m];
+                    }
                     pc[i] = cols[pcol[i]];
                 }
             }
@@ -298,6 +312,31 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
             }
             if (stg[0]) store_window();
             __syncthreads();   // pair tables and the first half's window complete
+            // This thread's voxel column (slice m, in-slice index q) takes the pairs of slice m
+            // whose xi lies within one voxel of q: the first is found by binary search (xi is
+            // monotone along a slice's pairs), the count by a scan; both serve both halves.
+            const float gq = (float)(axis == 0 ? tj : ti);
+            int gfirst = 0, gcnt = 0;
+            {
+                const int m = axis == 0 ? ti : tj;
+                const int n = colN[m];
+                const float *__restrict__ xs = xiq + pfx[m];
+                gfirst = pfx[m];
+                if (n > 0) {
+                    const float sgn = (n >= 2 && xs[n - 1] < xs[0]) ? -1.0f : 1.0f;
+                    // first pair with sgn*xi > sgn*q - 1 (sgn*xi increases along the slice)
+                    int lo = 0, hi = n;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (sgn * xs[mid] > sgn * gq - 1.0f) hi = mid;
+                        else lo = mid + 1;
+                    }
+                    int e = lo;
+                    while (e < n && sgn * xs[e] < sgn * gq + 1.0f) ++e;
+                    gfirst += lo;
+                    gcnt = e - lo;
+                }
+            }
 
             auto half_pass = [&](auto hc) {
                 constexpr int h = decltype(hc)::value;
@@ -370,30 +409,15 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                     }
                 }
                 __syncthreads();
-                // 4. each thread gathers its voxel column (m, q) from the columns near q
-                const int m = axis == 0 ? ti : tj;
-                const float q = (float)(axis == 0 ? tj : ti);
-                const int n = colN[m];
-                if (n > 0) {
-                    const float *__restrict__ xs = xiq + pfx[m];
-                    const float sgn = (n >= 2 && xs[n - 1] < xs[0]) ? -1.0f : 1.0f;
-                    // first pair with sgn*xi > sgn*q - 1 (sgn*xi increases along the slice)
-                    int lo = 0, hi = n;
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (sgn * xs[mid] > sgn * q - 1.0f) hi = mid;
-                        else lo = mid + 1;
-                    }
-                    for (int pp = lo; pp < n; ++pp) {
-                        const float xv = xs[pp];
-                        if (!(sgn * xv < sgn * q + 1.0f)) break;
-                        const float w = 1.0f - fabsf(xv - q);
-                        if (w > 0.0f) {
-                            const float *__restrict__ zp = Z + pfx[m] + pp;
+                // 4. each thread adds to its voxel column the profiles of the pairs found below
+#pragma unroll 2
+                for (int j = 0; j < gcnt; ++j) {
+                    const int pp = gfirst + j;
+                    const float w = 1.0f - fabsf(xiq[pp] - gq);
+                    if (w > 0.0f) {
 #pragma unroll
-                            for (int kk = 0; kk < kKH; ++kk)
-                                acc[h * kKH + kk] = fmaf(w, zp[kk * NPM], acc[h * kKH + kk]);
-                        }
+                        for (int kk = 0; kk < kKH; ++kk)
+                            acc[h * kKH + kk] = fmaf(w, Z[kk * NPM + pp], acc[h * kKH + kk]);
                     }
                 }
             };
