@@ -220,6 +220,9 @@ def paper_shaped_run(fbl, syn, seconds: float, views: int = 72, n: int = 560, n0
             st["series"].append({"t": round(el, 3), "k": it.k + 1, "epoch": it.epoch, "batch": len(it.batch),
                                  "re": re})
             st["next"] = el + max(0.5, seconds / 60.0)
+            if len(st["series"]) % 10 == 1:
+                log("paper-shaped run: %.1f s, iteration %d, epoch %d, batch %d, RE %.4f"
+                    % (el, it.k + 1, it.epoch, len(it.batch), re))
         st["excluded"] += time.perf_counter() - t_in
         if el >= seconds:
             raise Budget()
@@ -248,6 +251,53 @@ def paper_shaped_run(fbl, syn, seconds: float, views: int = 72, n: int = 560, n0
     }
 
 
+def kernel_scaling(fbl, syn, names, reps=5):
+    """Projector and step kernel times alone at several workload sizes, on a voxelised phantom
+    and a seeded residual (no measured data needed): forward, backprojection and prox trial
+    of one mini-batch of the workload's size, mean over `reps` launches after one warm-up."""
+    import torch
+    out = []
+    for name in names:
+        cfg = syn.CONFIGS[name]
+        g = syn.config_geometry(name)
+        B = cfg["batch"]
+        t0 = time.perf_counter()
+        _, xt = syn.phantom(g, cfg["k"], seed=1000 * int(name[1:]), hi=cfg["hi"], sub=1)
+        x = torch.from_numpy(xt.astype(np.float32)).cuda()
+        del xt
+        views = syn.view_permutations(g.n_views, 1, seed=7)[0][:B]
+        r = torch.from_numpy(syn.random_projections(g, B, seed=8, scale=0.1)).cuda()
+        with fbl.Plan(g, max_batch=B) as plan:
+            plan_s = time.perf_counter() - t0
+            y = fbl.fb_lisa_forward(plan, x, views)
+            gr = fbl.fb_lisa_backproject(plan, r, views)
+            xb, red = fbl.fb_lisa_step(plan, x, gr, 1e-3, 0.0, 0.0, math.inf)
+            torch.cuda.synchronize()
+            plan.timing(True)
+            for _ in range(reps):
+                fbl.fb_lisa_forward(plan, x, views, y=y)
+                fbl.fb_lisa_backproject(plan, r, views, g=gr)
+                fbl.fb_lisa_step(plan, x, gr, 1e-3, 0.0, 0.0, math.inf, xbar=xb, red=red)
+            torch.cuda.synchronize()
+            kt = plan.timing_read()
+        t = {k: ms / n * 1e-3 for k, (ms, n) in kt.items() if n}
+        byts = B * (g.d * 4 + 4 * g.n_p)
+        rec = {"workload": "%s: %d^3, %d views, %dx%d detector, batch %d" % (name, g.nx, g.n_views, g.nu, g.nv, B),
+               "setup_s": round(plan_s, 1),
+               "forward_us": round(t["forward"] * 1e6, 1), "backproject_us": round(t["backproject"] * 1e6, 1),
+               "step_us": round(t["step"] * 1e6, 1),
+               "forward_gups": round(g.d * B / t["forward"] / 1e9, 1),
+               "backproject_gups": round(g.d * B / t["backproject"] / 1e9, 1),
+               "forward_hbm_frac": round(byts / t["forward"] / 8e12, 4),
+               "backproject_hbm_frac": round(byts / t["backproject"] / 8e12, 4),
+               "step_hbm_frac": round(12 * g.d / t["step"] / 8e12, 4)}
+        log(json.dumps(rec))
+        out.append(rec)
+        del x, r, y, gr, xb
+        torch.cuda.empty_cache()
+    return {"mode": "kernel scaling", "fp32": out}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +313,9 @@ def main(argv=None):
     ap.add_argument("--paper-run", type=float, default=0.0, metavar="SECONDS",
                     help="instead of the benchmark: the paper's growing-batch variant with mu > 0 on a 560^3 / "
                          "72-view synthetic stand-in, for this many seconds")
+    ap.add_argument("--kernels", default="", metavar="CONFIGS",
+                    help="instead of the benchmark: time the projector and step kernels alone at these workloads "
+                         "(comma-separated, e.g. c3,c5)")
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -277,6 +330,9 @@ def main(argv=None):
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.kernels:
+        print(json.dumps(kernel_scaling(fbl, syn, [c for c in args.kernels.split(",") if c])), flush=True)
+        return 0
     if args.paper_run > 0:
         print(json.dumps(paper_shaped_run(fbl, syn, args.paper_run)), flush=True)
         return 0
