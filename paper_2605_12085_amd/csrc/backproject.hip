@@ -39,7 +39,7 @@ constexpr int kKQ = 4;         // z-entries per profile work item
 static_assert(kKH == 2 * kKQ, "a half pass has two profile items per pair");
 constexpr int kThreads = 256;
 constexpr int kRowPad = 8;     // zero rows above and below the staged residual window
-constexpr int kWinRows = 32;   // staged rows per column (longer spans read global memory)
+constexpr int kWinRows = 28;   // staged rows per column (longer spans read global memory)
 constexpr int kWinStride = kWinRows + 2 * kRowPad + 1;   // odd: lanes on adjacent columns use distinct banks
 constexpr int kWinExtra = 16;  // columns the 16 slices' ranges may add to one slice's
 
@@ -77,11 +77,12 @@ template <int NC, typename Fetch, typename Store>
 __device__ __forceinline__ void pair_profile(float a0, float rowz, float inv, int kk0, float t_lo, float t_hi,
                                              Fetch fetch, Store store)
 {
-    const float am1 = -1.0f - a0;
+    const float c1 = fmaf(-1.0f - a0, inv, 1.0f);
 #pragma unroll
     for (int j = 0; j < kKQ; ++j) {
-        const float rho = ((float)(kk0 + j) + am1) * inv;   // e_t = kk - 1 at t = rho
-        const float tf = __builtin_amdgcn_fmed3f(floorf(rho) + 1.0f, t_lo, t_hi);
+        // e_t = kk - 1 at t = rho; the first candidate is floor(rho) + 1 = floor(rho + 1)
+        const float rho1 = fmaf((float)(kk0 + j), inv, c1);
+        const float tf = __builtin_amdgcn_fmed3f(floorf(rho1), t_lo, t_hi);
         const int t0 = (int)tf;
         float d = fmaf(rowz, tf, a0 - (float)(kk0 + j));
         float s = 0.0f;
@@ -110,6 +111,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
     __shared__ float Z[kKH * NPM];                    // Z[k][pair]: half-pass z-profile of each pair
     __shared__ float xiq[NPM];                        // xi of the pair's column on its slice, minus q0
     __shared__ float prz[NPM];                        // row spacing in eta there; 0 if xi misses the tile
+    __shared__ float pinv[NPM];                       // its reciprocal
     __shared__ float pa0[2][NPM];                     // per half: eta of the pair's source row 0, minus the
                                                       // half's first z (window row 0 if staged, else detector row 0)
     __shared__ short pcr[NPM];                        // the pair's column minus the class window's c0
@@ -302,6 +304,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                     const bool in = xl > -1.0f && xl < (float)kTQ;
                     const double B = fma(fm, cp.t1, cp.t0) * dvz;   // tau dv/hz: eta per detector row
                     prz[p] = in ? (float)B : 0.0f;
+                    pinv[p] = in ? 1.0f / (float)B : 0.0f;
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         const double row0 = stg[h] ? (double)(r0h[h] - kRowPad) : 0.0;
@@ -371,7 +374,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                             const float r = prz[p];
                             ok[u] = it < nItems && r != 0.0f;
                             rz[u] = ok[u] ? r : 1.0f;
-                            inv[u] = 1.0f / rz[u];
+                            inv[u] = ok[u] ? pinv[p] : 1.0f;
                             a0[u] = ok[u] ? pa0[h][p] : 0.0f;
                             wofs[u] = pcr[p] * kWinStride;
                             pr[u] = p;
@@ -400,7 +403,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                         // detector rows directly (rows outside [0, nv) do not exist)
                         const float *__restrict__ src = rwv + c0 + pcr[pr];
                         const int64_t nu = geo.nu;
-                        pair_profile<NC>(pa0[h][pr], rz, 1.0f / rz, kq * kKQ, 0.0f, (float)max(0, geo.nv - NC),
+                        pair_profile<NC>(pa0[h][pr], rz, pinv[pr], kq * kKQ, 0.0f, (float)max(0, geo.nv - NC),
                                          [&](int t) {
                                              const float v = src[(int64_t)min(t, geo.nv - 1) * nu];
                                              return t < geo.nv ? v : 0.0f;
