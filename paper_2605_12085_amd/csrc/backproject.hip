@@ -15,13 +15,27 @@
 //   1. finds, per slice of the tile, the detector columns whose ray plane crosses the
 //      tile, and lists the (slice, column) pairs with their xi and ray parameter;
 // then, for each half of the tile's z-range,
-//   2. stages the weighted residual of those columns and of the rows that reach the
-//      half's z-range in LDS (zero-padded above and below);
-//   3. gathers each pair's 8-entry z-profile from the few rows within one voxel of each
-//      k (rows are equally spaced in eta, so the candidates are consecutive), a quarter
-//      of the work items per pair so that every lane has about the same load;
+//   2. reads the weighted residual of those columns on the rows that reach the half's
+//      z-range and keeps, per column, two prefix sums over its rows in LDS: of the
+//      residual and of the residual times the row index;
+//   3. forms each pair's 8-entry z-profile from those prefix sums (below);
 //   4. lets every thread add to its voxel column (m, q) the profiles of the columns whose
 //      xi lies within one voxel (binary search: xi is monotone along the slice's pairs).
+//
+// Profiles from prefix sums.  The hat is the second difference of the ramp
+// ramp(t) = max(0, t):  hat(e - k) = ramp(k + 1 - e) - 2 ramp(k - e) + ramp(k - 1 - e).
+// So Z(k) = H(k + 1) - 2 H(k) + H(k - 1) with H(y) = sum over rows with e_s < y of
+// (y - e_s) v_s, and since a pair's rows are equally spaced (e_s = a + b s),
+//   H(y) = (y - a) P(T) - b Q(T),  P(T) = sum_{s<T} v_s,  Q(T) = sum_{s<T} s v_s,
+// where T(y) is the number of rows below y.  Ten look-ups give the 8 entries of a half;
+// the column's two prefix arrays are shared by the pairs of all 16 slices.  A row whose
+// position is within rounding of y enters H(y) with weight y - e_s ~ 0, so T needs no
+// exact rounding, and rows below the window add an affine function of y to H, which
+// the second difference removes.  The cancellation in that difference is why the sums
+// are exact: each column's residuals are scaled by a power of two to at most 2^22 in
+// magnitude and rounded to integers (a relative change of at most 2^-23 of the
+// column's largest entry, the size of one FP32 rounding of it), their prefix sums are
+// exact 32-bit integers, and H and its second difference are taken in FP64.
 #include <climits>
 #include <type_traits>
 
@@ -38,9 +52,13 @@ constexpr int kKH = 8;         // z-entries per half pass
 constexpr int kKQ = 4;         // z-entries per profile work item
 static_assert(kKH == 2 * kKQ, "a half pass has two profile items per pair");
 constexpr int kThreads = 256;
-constexpr int kRowPad = 8;     // zero rows above and below the staged residual window
 constexpr int kWinRows = 28;   // staged rows per column (longer spans read global memory)
-constexpr int kWinStride = kWinRows + 2 * kRowPad + 1;   // odd: lanes on adjacent columns use distinct banks
+constexpr int kSegRows = kWinRows / 4;     // rows per lane: four lanes share a column
+static_assert(kWinRows % 4 == 0, "a column's rows split evenly over four lanes");
+constexpr int kPreStride = kWinRows + 1;   // prefix entries per column (odd: adjacent columns use distinct banks)
+constexpr int kRowCen = kWinRows / 2;      // row origin of the moment prefix (keeps it within 32 bits)
+constexpr int kQuantBits = 22;             // residuals are scaled to at most 2^22 in magnitude
+constexpr int kExpNonFinite = 1 << 20;     // scale exponent marking a column with a non-finite entry
 constexpr int kWinExtra = 16;  // columns the 16 slices' ranges may add to one slice's
 
 // rw = grad_scale * w * r: the per-ray path length per slice folded into the residual.
@@ -68,11 +86,13 @@ __device__ __forceinline__ float column_of(const Geo &geo, const ViewParam &vp, 
     return geo.sdd * lat / dep / geo.du + geo.cu;
 }
 
-// Part of the z-profile of one (slice, column) pair: Z(kk) = sum_t hat(e_t - kk) * val(t)
-// for kk = kk0 .. kk0 + kKQ - 1, where row t of the pair's source has e_t = a0 + rowz * t
-// (eta relative to the pass's first z) and inv = 1 / rowz.  The NC = ceil(2 / rowz)
-// candidates of each kk start at the first row with e_t > kk - 1, clamped to
-// [t_lo, t_hi]; store(kk, Z) receives each entry.
+// Part of the z-profile of one (slice, column) pair, tap by tap (the path for windows
+// too tall to stage): Z(kk) = sum_t hat(e_t - kk) * val(t) for kk = kk0 .. kk0 + kKQ - 1,
+// where row t of the pair's source has e_t = a0 + rowz * t (eta relative to the pass's
+// first z) and inv = 1 / rowz.  The NC candidates of each kk start at the first row with
+// e_t > kk - 1 as computed in FP32, clamped to [t_lo, t_hi]; NC = ceil(2 / rowz) + 1, one
+// more than the rows in reach, covers a start one row early by rounding.  store(kk, Z)
+// receives each entry.
 template <int NC, typename Fetch, typename Store>
 __device__ __forceinline__ void pair_profile(float a0, float rowz, float inv, int kk0, float t_lo, float t_hi,
                                              Fetch fetch, Store store)
@@ -104,18 +124,16 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
 {
     constexpr int NPM = kTQ * WP;                     // pair slots: 16 slices x WP columns
     constexpr int kWinCols = WP + kWinExtra;          // column union of the 16 slices
-    constexpr int kWinSize = kWinCols * kWinStride;
-    constexpr int kColSweeps = (kWinCols + 63) / 64;        // window columns per lane
-    constexpr int kRowIters = (kWinStride + 3) / 4;         // window rows per wave
+    constexpr int kColSweeps = (kWinCols + 63) / 64;  // window columns: 16 per wave and sweep
     constexpr int kPairIters = (NPM + kThreads - 1) / kThreads;
     __shared__ float Z[kKH * NPM];                    // Z[k][pair]: half-pass z-profile of each pair
     __shared__ float xiq[NPM];                        // xi of the pair's column on its slice, minus q0
     __shared__ float prz[NPM];                        // row spacing in eta there; 0 if xi misses the tile
-    __shared__ float pinv[NPM];                       // its reciprocal
     __shared__ float pa0[2][NPM];                     // per half: eta of the pair's source row 0, minus the
                                                       // half's first z (window row 0 if staged, else detector row 0)
     __shared__ short pcr[NPM];                        // the pair's column minus the class window's c0
-    __shared__ float win[kWinSize];                   // residual window, column-major, zero-padded rows
+    __shared__ int2 pre[kWinCols * kPreStride];       // per window column and T: (P(T), Q(T)), integers
+    __shared__ int pexp[kWinCols];                    // per window column: residual scale exponent
     __shared__ int colA[kTQ], colN[kTQ], pfx[kTQ];    // per slice: first column, count, first pair
 
     const int tid = threadIdx.x;
@@ -238,34 +256,82 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 stg[h] = nRh[h] > 0 && nRh[h] <= kWinRows && nC <= kWinCols;
             }
             // The pairs' column parameters and the first half's residual window are loaded
-            // together, before either is used.  Window row t holds detector row
-            // r0 - kRowPad + t (zero outside [kRowPad, kRowPad + nR)); lanes run along
-            // columns (contiguous in memory), waves along rows.  The second half's window is
-            // loaded when that half starts (holding it in registers across the first half
-            // would cost occupancy).
-            float wv[kColSweeps][kRowIters];
+            // together, before either is used; the second half's window is loaded after
+            // the first half's profiles, so that it arrives during that half's gather.
+            // Window row t is detector row r0 + t (zero for t >= nR).  Four lanes share a
+            // window column (lanes c, c + 16, c + 32, c + 48 of a wave), each holding
+            // kSegRows consecutive rows.
+            const int wcol = (lane & 15) + 16 * wave, wseg = lane >> 4;
+            float wv[kColSweeps][kSegRows];
+            // Loads are unconditional, from a clamped (always valid) row and column, so that
+            // they issue back to back without branches and stay in flight until the prefix
+            // sums use them; build_prefix masks the clamped entries.  A clamped load repeats
+            // an entry of the same column's window (or reads a column that is not kept), so
+            // a non-finite value it brings in belongs to that window anyway.
             auto load_window = [&](int h) {
+                const int lim = (nRh[h] - 1) * geo.nu;
+                const float *__restrict__ rowbase = rwv + (int64_t)r0h[h] * geo.nu + c0;
 #pragma unroll
                 for (int cs = 0; cs < kColSweeps; ++cs) {
-                    const int col = lane + 64 * cs;
+                    const float *__restrict__ src = rowbase + min(wcol + 64 * cs, nC - 1);
+                    int off = wseg * kSegRows * geo.nu;
 #pragma unroll
-                    for (int i = 0; i < kRowIters; ++i) {
-                        const int t = wave + 4 * i;
-                        const bool ld = col < nC && t >= kRowPad && t < kRowPad + nRh[h];
-                        wv[cs][i] = ld ? rwv[(int64_t)(r0h[h] - kRowPad + t) * geo.nu + c0 + col] : 0.0f;
+                    for (int j = 0; j < kSegRows; ++j) {
+                        wv[cs][j] = src[min(off, lim)];
+                        off += geo.nu;
                     }
                 }
             };
-            auto store_window = [&]() {
+            // Prefix sums of the loaded window: the column's scale exponent from its largest
+            // magnitude (two exchanges among its four lanes), each lane's running sums over
+            // its rows, then the sums of the lanes below it added (an inclusive scan over the
+            // four lanes).  |q| <= 2^22 keeps |P| < 2^27 and |Q| < 196 * 2^22 < 2^31.
+            auto build_prefix = [&](int h) {
 #pragma unroll
                 for (int cs = 0; cs < kColSweeps; ++cs) {
-                    const int col = lane + 64 * cs;
-                    if (col < nC) {
+                    const int col = wcol + 64 * cs;
 #pragma unroll
-                        for (int i = 0; i < kRowIters; ++i) {
-                            const int t = wave + 4 * i;
-                            if (t < kWinStride) win[col * kWinStride + t] = wv[cs][i];
+                    for (int j = 0; j < kSegRows; ++j) {
+                        const bool keep = col < nC && wseg * kSegRows + j < nRh[h];
+                        wv[cs][j] = keep ? wv[cs][j] : 0.0f;
+                    }
+                    float mx = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < kSegRows; ++j) mx = fmaxf(mx, fabsf(wv[cs][j]));
+                    mx = fmaxf(mx, __shfl_xor(mx, 16));
+                    mx = fmaxf(mx, __shfl_xor(mx, 32));
+                    const bool fin = mx <= 3.4028235e38f;   // false for inf and NaN
+                    int ex;
+                    (void)frexpf(fin ? mx : 1.0f, &ex);      // mx < 2^ex
+                    const int kx = kQuantBits - ex;
+                    int P = 0, Q = 0, ps[kSegRows], qs[kSegRows];
+#pragma unroll
+                    for (int j = 0; j < kSegRows; ++j) {
+                        const int q = fin ? (int)rintf(ldexpf(wv[cs][j], kx)) : 0;
+                        P += q;
+                        Q += (wseg * kSegRows + j - kRowCen) * q;
+                        ps[j] = P;
+                        qs[j] = Q;
+                    }
+                    int iP = P, iQ = Q;
+                    {
+                        const int uP = __shfl_up(iP, 16), uQ = __shfl_up(iQ, 16);
+                        if (wseg >= 1) { iP += uP; iQ += uQ; }
+                    }
+                    {
+                        const int uP = __shfl_up(iP, 32), uQ = __shfl_up(iQ, 32);
+                        if (wseg >= 2) { iP += uP; iQ += uQ; }
+                    }
+                    const int oP = iP - P, oQ = iQ - Q;   // sums of the rows below this lane's
+                    if (col < nC) {
+                        int2 *__restrict__ dst = pre + col * kPreStride;
+                        if (wseg == 0) {
+                            dst[0] = make_int2(0, 0);
+                            pexp[col] = fin ? kx : kExpNonFinite;
                         }
+#pragma unroll
+                        for (int j = 0; j < kSegRows; ++j)
+                            dst[wseg * kSegRows + j + 1] = make_int2(ps[j] + oP, qs[j] + oQ);
                     }
                 }
             };
@@ -304,17 +370,16 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                     const bool in = xl > -1.0f && xl < (float)kTQ;
                     const double B = fma(fm, cp.t1, cp.t0) * dvz;   // tau dv/hz: eta per detector row
                     prz[p] = in ? (float)B : 0.0f;
-                    pinv[p] = in ? 1.0f / (float)B : 0.0f;
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        const double row0 = stg[h] ? (double)(r0h[h] - kRowPad) : 0.0;
+                        const double row0 = stg[h] ? (double)r0h[h] : 0.0;
                         pa0[h][p] = (float)fma(B, row0 - (double)geo.cv, geo.cz - (double)(k0 + h * kKH));
                     }
                     pcr[p] = (short)(pcol[i] - c0);
                 }
             }
-            if (stg[0]) store_window();
-            __syncthreads();   // pair tables and the first half's window complete
+            if (stg[0]) build_prefix(0);
+            __syncthreads();   // pair tables and the first half's prefix sums complete
             // This thread's voxel column (slice m, in-slice index q) takes the pairs of slice m
             // whose xi lies within one voxel of q: the first is found by binary search (xi is
             // monotone along a slice's pairs), the count by a scan; both serve both halves.
@@ -341,60 +406,47 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 }
             }
 
-            auto half_pass = [&](auto hc) {
+            // 3. profiles of the pairs that meet the tile, for half h
+            auto profiles = [&](auto hc) {
                 constexpr int h = decltype(hc)::value;
-                const int nR = nRh[h];
-                if (nR <= 0) return;   // uniform across the block
-                const bool staged = stg[h];
-                if (h == 1) {
-                    // the first half's profiles, the window's only readers, ended at the
-                    // barrier before its gather; this barrier also ends that gather (Z)
-                    if (staged) {
-                        load_window(1);
-                        store_window();
-                    }
-                    __syncthreads();
-                }
-                // 3. profiles: item (pair, quarter of the half's z-range)
-                const int nItems = (kKH / kKQ) * NP;
-                if (staged) {
-                    // Two items per lane and round, without branches: an item that needs no
-                    // profile (the pair misses the tile, or the index runs past the end)
-                    // computes on harmless stand-in values and skips its stores, so the two
-                    // items' dependent LDS reads and arithmetic overlap.
-                    for (int it0 = tid; it0 < nItems; it0 += 2 * kThreads) {
-                        float a0[2], rz[2], inv[2], zv[2][kKQ];
-                        int wofs[2], pr[2], kk0[2];
-                        bool ok[2];
+                if (stg[h]) {
+                    for (int p = tid; p < NP; p += kThreads) {
+                        const float rz = prz[p];
+                        if (rz == 0.0f) continue;   // xi misses the tile: no voxel reads this pair
+                        const float a0 = pa0[h][p];
+                        const int col = pcr[p];
+                        const int kx = pexp[col];
+                        const int2 *__restrict__ pc = pre + col * kPreStride;
+                        // T(y) = ceil((y - a0) / rz) clamped to the window; the approximate
+                        // reciprocal only moves rows at zero weight (see the file's head)
+                        const float inv = __builtin_amdgcn_rcpf(rz);
+                        const float ub = -a0 * inv;
+                        const double rzd = (double)rz;
+                        // -(eta of row kRowCen): H(y) = (y - that) P - rz Q with the moment
+                        // prefix taken about row kRowCen
+                        double nam = -fma(rzd, (double)kRowCen, (double)a0);
+                        if (kx == kExpNonFinite) nam = __builtin_nan("");
+                        int2 e[kKH + 2];
 #pragma unroll
-                        for (int u = 0; u < 2; ++u) {
-                            const int it = it0 + u * kThreads;
-                            int p = it < nItems ? it : 0, kq = 0;
-                            if (p >= NP) { p -= NP; kq = 1; }
-                            const float r = prz[p];
-                            ok[u] = it < nItems && r != 0.0f;
-                            rz[u] = ok[u] ? r : 1.0f;
-                            inv[u] = ok[u] ? pinv[p] : 1.0f;
-                            a0[u] = ok[u] ? pa0[h][p] : 0.0f;
-                            wofs[u] = pcr[p] * kWinStride;
-                            pr[u] = p;
-                            kk0[u] = kq * kKQ;
+                        for (int i = 0; i < kKH + 2; ++i) {
+                            const float u = fmaf((float)(i - 1), inv, ub);
+                            const int T = (int)__builtin_amdgcn_fmed3f(ceilf(u), 0.0f, (float)kWinRows);
+                            e[i] = pc[T];
                         }
+                        // all ten look-ups are in flight before the first is used
+                        __builtin_amdgcn_sched_barrier(0);
+                        double H[kKH + 2];
 #pragma unroll
-                        for (int u = 0; u < 2; ++u) {
-                            const float *__restrict__ wc = win + wofs[u];
-                            pair_profile<NC>(a0[u], rz[u], inv[u], kk0[u], 0.0f, (float)(kWinStride - NC),
-                                             [&](int t) { return wc[t]; },
-                                             [&](int kk, float z) { zv[u][kk - kk0[u]] = z; });
+                        for (int i = 0; i < kKH + 2; ++i)
+                            H[i] = fma((double)(i - 1) + nam, (double)e[i].x, -rzd * (double)e[i].y);
+#pragma unroll
+                        for (int kk = 0; kk < kKH; ++kk) {
+                            const double zd = (H[kk + 2] + H[kk]) - 2.0 * H[kk + 1];
+                            Z[kk * NPM + p] = ldexpf((float)zd, -kx);
                         }
-#pragma unroll
-                        for (int u = 0; u < 2; ++u)
-                            if (ok[u]) {
-#pragma unroll
-                                for (int j = 0; j < kKQ; ++j) Z[(kk0[u] + j) * NPM + pr[u]] = zv[u][j];
-                            }
                     }
                 } else {
+                    const int nItems = (kKH / kKQ) * NP;
                     for (int it = tid; it < nItems; it += kThreads) {
                         int pr = it, kq = 0;
                         if (pr >= NP) { pr -= NP; kq = 1; }
@@ -403,16 +455,19 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                         // detector rows directly (rows outside [0, nv) do not exist)
                         const float *__restrict__ src = rwv + c0 + pcr[pr];
                         const int64_t nu = geo.nu;
-                        pair_profile<NC>(pa0[h][pr], rz, pinv[pr], kq * kKQ, 0.0f, (float)max(0, geo.nv - NC),
-                                         [&](int t) {
-                                             const float v = src[(int64_t)min(t, geo.nv - 1) * nu];
-                                             return t < geo.nv ? v : 0.0f;
-                                         },
-                                         [&](int kk, float z) { Z[kk * NPM + pr] = z; });
+                        pair_profile<NC + 1>(pa0[h][pr], rz, 1.0f / rz, kq * kKQ, 0.0f,
+                                             (float)max(0, geo.nv - (NC + 1)),
+                                             [&](int t) {
+                                                 const float v = src[(int64_t)min(t, geo.nv - 1) * nu];
+                                                 return t < geo.nv ? v : 0.0f;
+                                             },
+                                             [&](int kk, float z) { Z[kk * NPM + pr] = z; });
                     }
                 }
-                __syncthreads();
-                // 4. each thread adds to its voxel column the profiles of the pairs found below
+            };
+            // 4. each thread adds to its voxel column the profiles of the pairs found above
+            auto gather = [&](auto hc) {
+                constexpr int h = decltype(hc)::value;
 #pragma unroll 2
                 for (int j = 0; j < gcnt; ++j) {
                     const int pp = gfirst + j;
@@ -424,10 +479,19 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                     }
                 }
             };
-            // half 1 overwrites Z only after the barrier that follows its staging, which every
-            // thread reaches once its half-0 gather is done
-            half_pass(std::integral_constant<int, 0>{});
-            half_pass(std::integral_constant<int, 1>{});
+            using H0 = std::integral_constant<int, 0>;
+            using H1 = std::integral_constant<int, 1>;
+            if (nRh[0] > 0) profiles(H0{});   // uniform across the block, as are nRh and stg
+            if (stg[1]) load_window(1);
+            __syncthreads();   // half-0 profiles complete; the prefix sums' readers are done
+            if (nRh[0] > 0) gather(H0{});
+            if (nRh[1] > 0) {
+                if (stg[1]) build_prefix(1);
+                __syncthreads();   // half-1 prefix sums complete; the half-0 gather is done with Z
+                profiles(H1{});
+                __syncthreads();
+                gather(H1{});
+            }
         }
     }
     const int i = i0 + ti, j = j0 + tj;
