@@ -79,11 +79,13 @@ __global__ __launch_bounds__(256) void prescale_kernel(const float *__restrict__
 }
 
 // Detector column index (fractional) of the ray through the point (X, Y) mm (any z).
+// Only column ranges with a column of margin are built from it, so the hardware
+// reciprocal (within a few units in the last place) serves instead of a division.
 __device__ __forceinline__ float column_of(const Geo &geo, const ViewParam &vp, float X, float Y)
 {
     const float lat = -X * vp.s + Y * vp.c;
     const float dep = geo.sod - (X * vp.c + Y * vp.s);
-    return geo.sdd * lat / dep / geo.du + geo.cu;
+    return fmaf(geo.sdd * lat, __builtin_amdgcn_rcpf(dep * geo.du), geo.cu);
 }
 
 // Part of the z-profile of one (slice, column) pair, tap by tap (the path for windows
@@ -135,6 +137,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
     __shared__ int2 pre[kWinCols * kPreStride];       // per window column and T: (P(T), Q(T)), integers
     __shared__ int pexp[kWinCols];                    // per window column: residual scale exponent
     __shared__ int colA[kTQ], colN[kTQ], pfx[kTQ];    // per slice: first column, count, first pair
+    __shared__ int cspan[3];                          // the class window's first and last column, pair count
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -179,11 +182,13 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
             const int mt0 = axis == 0 ? i0 : j0;       // first slice of the tile
             const int q0 = axis == 0 ? j0 : i0;        // first in-slice index of the tile
             __syncthreads();   // the previous class's readers are done with the shared arrays
-            // 1. per-slice column ranges
-            if (tid < kTQ) {
-                const int mg = mt0 + tid;
+            // 1. per-slice column ranges (lanes 0..15 of wave 0), each slice's first pair (a
+            //    prefix sum over those lanes) and the class window's columns [c0, c1], the
+            //    union of the slices' ranges (a reduction over them), by lane exchanges
+            if (wave == 0) {
+                const int mg = mt0 + lane;
                 int a = 0, n = 0;
-                if (mg < na) {
+                if (lane < kTQ && mg < na) {
                     const float fm = (float)mg;
                     float u0, u1;
                     if (axis == 0) {
@@ -200,46 +205,47 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                     const int b = min(cl1, (int)ceilf(fminf(hi, (float)geo.nu + 4.0f)) + 1);
                     n = min(WP, max(0, b - a + 1));
                 }
-                colA[tid] = a;
-                colN[tid] = n;
+                int incl = n;   // lanes >= kTQ hold no slice (n = 0)
+#pragma unroll
+                for (int off = 1; off < kTQ; off <<= 1) {
+                    const int t = __shfl_up(incl, off);
+                    if (lane >= off) incl += t;
+                }
+                int lo = n > 0 ? a : INT_MAX, hi = n > 0 ? a + n - 1 : -1;
+#pragma unroll
+                for (int off = 1; off < kTQ; off <<= 1) {   // within aligned groups of kTQ lanes
+                    lo = min(lo, __shfl_xor(lo, off));
+                    hi = max(hi, __shfl_xor(hi, off));
+                }
+                if (lane < kTQ) {
+                    colA[lane] = a;
+                    colN[lane] = n;
+                    pfx[lane] = incl - n;
+                }
+                if (lane == kTQ - 1) {
+                    cspan[0] = lo;
+                    cspan[1] = hi;
+                    cspan[2] = incl;
+                }
             }
             __syncthreads();
-            // the class window's columns [c0, c1] (union of the slices' ranges), the pair
-            // count and each slice's first pair (every thread forms them alike)
-            // The slice table is read into registers first (no LDS write in between, so the
-            // reads are not serialised), then reduced.
-            int sA[kTQ], sN[kTQ];
-#pragma unroll
-            for (int m = 0; m < kTQ; ++m) {
-                sA[m] = colA[m];
-                sN[m] = colN[m];
-            }
-            int c0 = INT_MAX, c1 = -1, NP = 0, myfirst = 0;
-#pragma unroll
-            for (int m = 0; m < kTQ; ++m) {
-                if (tid == m) myfirst = NP;
-                if (sN[m] > 0) {
-                    c0 = min(c0, sA[m]);
-                    c1 = max(c1, sA[m] + sN[m] - 1);
-                }
-                NP += sN[m];
-            }
-            if (tid < kTQ) pfx[tid] = myfirst;   // read after the barrier that ends the set-up
+            const int c0 = cspan[0], c1 = cspan[1], NP = cspan[2];
             if (c1 < 0) continue;   // uniform across the block
             const int nC = c1 - c0 + 1;
             // extremes of the ray parameter over the class's pairs: tau is monotone along
             // a detector row (inversely proportional to the column's D_a, which is affine
             // in the column) and affine in the slice, so they sit at the corner (first/last
             // column, first/last slice) pairs; a detector row of a given height is monotone
-            // in tau.  Bounds are taken in FP32 (rounding is far below the one-row margins).
+            // in tau.  Bounds are taken in FP32 with the hardware reciprocal (rounding is far
+            // below the one-row margins).
             float imin, imax;
             {
                 const int mA = mt0, mB = min(mt0 + kTQ - 1, na - 1);
                 const ColParam ca = cols[c0], cb = cols[c1];
                 const double t00 = fma((double)mA, ca.t1, ca.t0), t01 = fma((double)mB, ca.t1, ca.t0);
                 const double t10 = fma((double)mA, cb.t1, cb.t0), t11 = fma((double)mB, cb.t1, cb.t0);
-                imin = 1.0f / (float)(fmax(fmax(t00, t01), fmax(t10, t11)) * dvz);
-                imax = 1.0f / (float)(fmin(fmin(t00, t01), fmin(t10, t11)) * dvz);
+                imin = __builtin_amdgcn_rcpf((float)(fmax(fmax(t00, t01), fmax(t10, t11)) * dvz));
+                imax = __builtin_amdgcn_rcpf((float)(fmin(fmin(t00, t01), fmin(t10, t11)) * dvz));
             }
             // per half: detector rows that can reach z in (kb - 1, kb + kKH), kb = k0 + h kKH
             int r0h[2], nRh[2];
@@ -336,35 +342,23 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 }
             };
             if (stg[0]) load_window(0);
+            // Pair tables: the 16 threads of group tid / 16 take the pairs of slice tid / 16,
+            // one in every 16 (kPairIters = WP / 16 rounds cover the slice's at most WP).
+            static_assert(kThreads == kTQ * 16 && WP % 16 == 0, "16 threads per slice");
+            const int sm = tid >> 4, si = tid & 15;
+            const int sA = colA[sm], sN = colN[sm], sF = pfx[sm];
             ColParam pc[kPairIters];
-            int pm[kPairIters], pcol[kPairIters];
 #pragma unroll
-            for (int i = 0; i < kPairIters; ++i) {
-                const int p = tid + i * kThreads;
-                pm[i] = -1;
-                pcol[i] = 0;
-                if (p < NP) {
-                    // the slice whose pairs [start, start + n) hold p, from the registers
-                    int start = 0;
-#pragma unroll
-                    for (int m = 0; m < kTQ; ++m) {
-                        if (p >= start && p < start + sN[m]) {
-                            pm[i] = m;
-                            pcol[i] = sA[m] + (p - start);
-                        }
-                        start += sN[m];
-                    }
-                    pc[i] = cols[pcol[i]];
-                }
-            }
+            for (int i = 0; i < kPairIters; ++i)
+                if (si + 16 * i < sN) pc[i] = cols[sA + si + 16 * i];
             // 2. pair geometry: xi for the voxel gather, the ray parameter for the profile
 #pragma unroll
             for (int i = 0; i < kPairIters; ++i) {
-                const int p = tid + i * kThreads;
-                if (pm[i] >= 0) {
-                    const int m = pm[i];
+                const int cl = si + 16 * i;
+                if (cl < sN) {
+                    const int p = sF + cl;
                     const ColParam &cp = pc[i];
-                    const double fm = (double)(mt0 + m);
+                    const double fm = (double)(mt0 + sm);
                     const float xl = (float)(fma(fm, cp.xi1, cp.xi0) - (double)q0);
                     xiq[p] = xl;
                     const bool in = xl > -1.0f && xl < (float)kTQ;
@@ -375,7 +369,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                         const double row0 = stg[h] ? (double)r0h[h] : 0.0;
                         pa0[h][p] = (float)fma(B, row0 - (double)geo.cv, geo.cz - (double)(k0 + h * kKH));
                     }
-                    pcr[p] = (short)(pcol[i] - c0);
+                    pcr[p] = (short)(sA + cl - c0);
                 }
             }
             if (stg[0]) build_prefix(0);

@@ -428,7 +428,9 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
                     }
             }
         }
-        const int need = max_n + 1;   // one column of margin for FP contraction differences
+        // two columns of margin: the device forms the same ranges with FP contraction and
+        // a hardware reciprocal, which can move each end by one column
+        const int need = max_n + 2;
         const int sizes[] = {32, 48, 64};
         p->bp_pairs = 0;
         for (int sz : sizes)
