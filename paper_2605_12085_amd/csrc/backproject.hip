@@ -411,10 +411,12 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                         const int col = pcr[p];
                         const int kx = pexp[col];
                         const int2 *__restrict__ pc = pre + col * kPreStride;
-                        // T(y) = ceil((y - a0) / rz) clamped to the window; the approximate
-                        // reciprocal only moves rows at zero weight (see the file's head)
+                        // T(y) = ceil((y - a0) / rz) clamped to the window, taken as the
+                        // truncation of (y - a0) / rz + 1 (one more only where a row sits
+                        // exactly at y); that and the approximate reciprocal only move rows
+                        // at zero weight (see the file's head)
                         const float inv = __builtin_amdgcn_rcpf(rz);
-                        const float ub = -a0 * inv;
+                        const float ub = fmaf(-a0, inv, 1.0f);
                         const double rzd = (double)rz;
                         // -(eta of row kRowCen): H(y) = (y - that) P - rz Q with the moment
                         // prefix taken about row kRowCen
@@ -424,7 +426,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
 #pragma unroll
                         for (int i = 0; i < kKH + 2; ++i) {
                             const float u = fmaf((float)(i - 1), inv, ub);
-                            const int T = (int)__builtin_amdgcn_fmed3f(ceilf(u), 0.0f, (float)kWinRows);
+                            const int T = (int)__builtin_amdgcn_fmed3f(u, 0.0f, (float)kWinRows + 0.5f);
                             e[i] = pc[T];
                         }
                         // all ten look-ups are in flight before the first is used
@@ -462,15 +464,15 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
             // 4. each thread adds to its voxel column the profiles of the pairs found above
             auto gather = [&](auto hc) {
                 constexpr int h = decltype(hc)::value;
+                // (the search admits only pairs with |xi - q| < 1; the clamp keeps a weight
+                // rounded at that edge from turning negative)
 #pragma unroll 2
                 for (int j = 0; j < gcnt; ++j) {
                     const int pp = gfirst + j;
-                    const float w = 1.0f - fabsf(xiq[pp] - gq);
-                    if (w > 0.0f) {
+                    const float w = fmaxf(1.0f - fabsf(xiq[pp] - gq), 0.0f);
 #pragma unroll
-                        for (int kk = 0; kk < kKH; ++kk)
-                            acc[h * kKH + kk] = fmaf(w, Z[kk * NPM + pp], acc[h * kKH + kk]);
-                    }
+                    for (int kk = 0; kk < kKH; ++kk)
+                        acc[h * kKH + kk] = fmaf(w, Z[kk * NPM + pp], acc[h * kKH + kk]);
                 }
             };
             using H0 = std::integral_constant<int, 0>;
