@@ -122,6 +122,7 @@ template <int WP, int NC>
 __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const float *__restrict__ rw, Geo geo,
                                                                         DeviceTables tab, ViewList vl, int nb,
                                                                         int first, int accumulate,
+                                                                        const int *__restrict__ order,
                                                                         float *__restrict__ g)
 {
     constexpr int NPM = kTQ * WP;                     // pair slots: 16 slices x WP columns
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int tiles_x = (geo.nx + kTQ - 1) / kTQ, tiles_y = (geo.ny + kTQ - 1) / kTQ;
-    const int tile = blockIdx.x;
+    const int tile = order[blockIdx.x];   // a permutation of the tiles (launch order)
     const int i0 = (tile % tiles_x) * kTQ;
     const int j0 = ((tile / tiles_x) % tiles_y) * kTQ;
     const int k0 = (tile / (tiles_x * tiles_y)) * kTK;
@@ -508,6 +509,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
 }  // namespace
 
 int backproject_tile() { return kTQ; }
+int backproject_tile_z() { return kTK; }
 
 hipError_t launch_prescale(const fbl_plan *p, const float *r, const ViewList &vl, int nb, int first,
                            double grad_scale, float *rw, hipStream_t st)
@@ -527,7 +529,7 @@ static hipError_t launch_bp_t(const fbl_plan *p, const float *rw, const ViewList
     DeviceTables tab{p->d_col, p->d_rowV, p->d_rowV2, p->d_view};
     const int tiles = ((p->geo.nx + kTQ - 1) / kTQ) * ((p->geo.ny + kTQ - 1) / kTQ) * ((p->geo.nz + kTK - 1) / kTK);
     hipLaunchKernelGGL((bp_kernel<WP, NC>), dim3(tiles), dim3(kThreads), 0, st, rw, p->geo, tab, vl, nb, first,
-                       accumulate ? 1 : 0, g);
+                       accumulate ? 1 : 0, p->d_bp_order, g);
     return hipGetLastError();
 }
 

@@ -79,6 +79,7 @@ struct fbl_plan {
     double *d_rowV;
     float *d_rowV2;
     fbl::ViewParam *d_view;
+    int *d_bp_order;              // backprojection tiles in launch order (most work first)
     double *d_partials;           // FP64 per-block partial sums
     int64_t n_partials;
     float *d_rw;                  // [max_batch][nv][nu] weighted residual for the backprojection
@@ -126,5 +127,6 @@ hipError_t launch_mlp_adam(float *prm, const float *grad, float *m, float *v, in
 
 int step_blocks(const fbl_plan *p);
 int backproject_tile();   // in-slice tile extent of the backprojection (voxels)
+int backproject_tile_z(); // its extent along z (voxels)
 
 }  // namespace fbl

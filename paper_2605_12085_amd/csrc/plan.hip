@@ -158,6 +158,7 @@ void free_plan(fbl_plan *p)
     (void)hipFree(p->d_rowV);
     (void)hipFree(p->d_rowV2);
     (void)hipFree(p->d_view);
+    (void)hipFree(p->d_bp_order);
     (void)hipFree(p->d_partials);
     (void)hipFree(p->d_rw);
     (void)hipFree(p->d_xt);
@@ -449,13 +450,34 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
         rowV[(size_t)iv] = v / g->hz;
         rowV2[(size_t)iv] = (float)(v * v);
     }
+    // Backprojection launch order: a tile's work grows with the views whose fan covers
+    // it, which is all of them near the rotation axis and fewer towards the corners, so
+    // tiles are issued by increasing distance of their centre from the axis: the most
+    // work first, the least at the end of the launch, where it shortens the tail.
+    std::vector<int> bp_order;
+    {
+        const int TQ = backproject_tile(), TK = backproject_tile_z();
+        const int tx = (int)((g->nx + TQ - 1) / TQ), ty = (int)((g->ny + TQ - 1) / TQ), tz = (int)((g->nz + TK - 1) / TK);
+        std::vector<double> r2((size_t)tx * ty);
+        for (int j = 0; j < ty; ++j)
+            for (int i = 0; i < tx; ++i) {
+                const double X = ((double)i * TQ + 0.5 * (TQ - 1) - 0.5 * (double)(g->nx - 1)) * g->hx;
+                const double Y = ((double)j * TQ + 0.5 * (TQ - 1) - 0.5 * (double)(g->ny - 1)) * g->hy;
+                r2[(size_t)j * tx + i] = X * X + Y * Y;
+            }
+        bp_order.resize((size_t)tx * ty * tz);
+        for (size_t t = 0; t < bp_order.size(); ++t) bp_order[t] = (int)t;
+        std::stable_sort(bp_order.begin(), bp_order.end(),
+                         [&](int a, int b) { return r2[(size_t)(a % (tx * ty))] < r2[(size_t)(b % (tx * ty))]; });
+    }
     p->fp_blocks_per_view = forward_blocks_per_view(G);
     const int64_t np_fp = (int64_t)max_batch * p->fp_blocks_per_view;
     const int64_t np_step = 3 * (int64_t)step_blocks(p);
     p->n_partials = np_fp > np_step ? np_fp : np_step;
 
     if ((rc = dev_upload(&p->d_col, col)) != FBL_OK || (rc = dev_upload(&p->d_rowV, rowV)) != FBL_OK ||
-        (rc = dev_upload(&p->d_rowV2, rowV2)) != FBL_OK || (rc = dev_upload(&p->d_view, vp)) != FBL_OK) {
+        (rc = dev_upload(&p->d_rowV2, rowV2)) != FBL_OK || (rc = dev_upload(&p->d_view, vp)) != FBL_OK ||
+        (rc = dev_upload(&p->d_bp_order, bp_order)) != FBL_OK) {
         std::string msg = g_err;
         free_plan(p);
         g_err = msg;
