@@ -140,6 +140,37 @@ def test_fine_detector_rows_forward_and_backprojection(fbl, orc):
     _cmp_vol(gg, g_ref, what="backprojection fine rows")
 
 
+def test_backproject_power_of_two_scaling_is_exact(fbl):
+    # The staged z-profiles round each column's residual window to integers relative to
+    # its largest entry; the rounding follows a power-of-two scale of the residual, so
+    # the result scales by exactly that power (no overflow or underflow here).
+    g = syn.config_geometry("c1")
+    rng = np.random.default_rng(21)
+    views = syn.view_permutations(g.n_views, 1, seed=21)[0][:6]
+    r = rng.standard_normal((len(views), g.nv, g.nu)).astype(np.float32)
+    with fbl.Plan(g, max_batch=6) as plan:
+        g0 = fbl.fb_lisa_backproject(plan, _t(r), views, grad_scale=1.0).cpu().numpy()
+        for e in (60, -60):
+            ge = fbl.fb_lisa_backproject(plan, _t(np.ldexp(r, e)), views, grad_scale=1.0).cpu().numpy()
+            assert np.array_equal(ge, np.ldexp(g0, e)), e
+
+
+def test_backproject_wide_dynamic_range(fbl, orc):
+    # Residual rows spanning eight decades within each detector column (a few rows 1e4
+    # times the rest, the rest down to 1e-4): the rounding is relative to each column's
+    # largest entry, so the result keeps the 1e-5 bar on the volume.
+    g = syn.config_geometry("c1")
+    rng = np.random.default_rng(22)
+    views = syn.view_permutations(g.n_views, 1, seed=22)[0][:6]
+    r = rng.standard_normal((len(views), g.nv, g.nu)) * 10.0 ** rng.uniform(-4, 0, (len(views), g.nv, 1))
+    r[:, rng.integers(0, g.nv, 5), :] *= 1e4
+    r = r.astype(np.float32)
+    ref = orc.backproject(g, r.astype(np.float64), views)
+    with fbl.Plan(g, max_batch=6) as plan:
+        gg = fbl.fb_lisa_backproject(plan, _t(r), views, grad_scale=1.0).cpu().numpy()
+    _cmp_vol(gg, ref, what="backprojection, wide dynamic range")
+
+
 def test_adjoint_identity_on_gpu(fbl):
     import torch
     g = syn.Geometry(40, 36, 30, 1.0, 1.0, 1.0, 60, 44, 1.4, 1.4, 400.0, 800.0, 16)
