@@ -345,7 +345,7 @@ def main(argv=None):
     clean = syn.ellipsoid_line_integrals(g, ells, np.arange(g.n_views))
     b32 = syn.add_noise(clean, 0.01, seed=seed + 1).astype(np.float32)
     del clean
-    perms = syn.view_permutations(g.n_views, args.warmup + args.steps, seed=seed + 2)
+    perms = syn.view_permutations(g.n_views, args.warmup + args.steps + 3, seed=seed + 2)
     log("setup (phantom, exact line integrals, noise): %.1f s" % (time.perf_counter() - t_setup))
 
     b_dev = torch.from_numpy(b32).cuda()
@@ -371,7 +371,10 @@ def main(argv=None):
     for k in range(args.warmup):
         run.iterate(perms[k][:B])
     torch.cuda.synchronize()
-    run.plan.timing(True)  # HIP events around every kernel launch, on the launch stream
+    # HIP events (on the launch stream) around the projector kernels' launches only: each
+    # bracketed launch adds two event records to the stream, so timing every launch of an
+    # iteration would slow the timed region itself
+    run.plan.timing(True, kernels=("forward", "backproject"))
     n_hist = len(run.history)
     t0 = time.perf_counter()
     for k in range(args.warmup, args.warmup + args.steps):
@@ -381,18 +384,28 @@ def main(argv=None):
     kt = run.plan.timing_read()
     run.plan.timing(False)
     timed = run.history[n_hist:]
+    # a short supplementary pass with every launch bracketed gives the other kernels' means
+    k0 = args.warmup + args.steps
+    run.plan.timing(True)
+    for k in range(k0, k0 + 3):
+        run.iterate(perms[k][:B])
+    torch.cuda.synchronize()
+    ks = run.plan.timing_read()
+    run.plan.timing(False)
     n_fp = kt["forward"][1]
     n_bp = kt["backproject"][1]
     updates = (n_fp + n_bp) * g.d * B
     wall = t1 - t0
     gups = updates / wall / 1e9
-    kernel_us = {k: round(ms / n * 1e3, 2) for k, (ms, n) in kt.items() if n}
-    t_fp = kt["forward"][0] / n_fp * 1e-3            # fp_kernel alone
-    t_bp = kt["backproject"][0] / n_bp * 1e-3        # bp_kernel alone
-    t_fin = kt["finalize"][0] / max(1, kt["finalize"][1]) * 1e-3
-    t_fp_call = (kt["forward"][0] + kt["transpose"][0]) / n_fp * 1e-3 + t_fin   # whole forward call
-    t_bp_call = (kt["backproject"][0] + kt["prescale"][0]) / n_bp * 1e-3
-    t_st = kt["step"][0] / kt["step"][1] * 1e-3                # step_kernel alone
+    kernel_us = {k: round(ms / n * 1e3, 2) for k, (ms, n) in ks.items() if n}
+    kernel_us.update({k: round(kt[k][0] / kt[k][1] * 1e3, 2) for k in ("forward", "backproject")})
+    t_fp = kt["forward"][0] / n_fp * 1e-3            # fp_kernel alone (timed region)
+    t_bp = kt["backproject"][0] / n_bp * 1e-3        # bp_kernel alone (timed region)
+    t_fin = ks["finalize"][0] / max(1, ks["finalize"][1]) * 1e-3
+    n_fp_s = max(1, ks["forward"][1])
+    t_fp_call = t_fp + ks["transpose"][0] / n_fp_s * 1e-3 + t_fin   # whole forward call
+    t_bp_call = t_bp + ks["prescale"][0] / max(1, ks["backproject"][1]) * 1e-3
+    t_st = ks["step"][0] / ks["step"][1] * 1e-3                # step_kernel alone
 
     # roofline of the dominant kernel (the projector kernel with the larger share of the
     # timed region): the per-view block model, each view reads the volume once and writes
@@ -449,7 +462,7 @@ def main(argv=None):
         "per_call_ms": {"forward": round(t_fp_call * 1e3, 4), "backproject": round(t_bp_call * 1e3, 4),
                         "step": round(t_st * 1e3, 4)},
         "gups_per_op": {"forward": round(g.d * B / t_fp / 1e9, 2), "backproject": round(g.d * B / t_bp / 1e9, 2)},
-        "calls": {"forward": n_fp, "backproject": n_bp, "step": kt["step"][1]},
+        "calls": {"forward": n_fp, "backproject": n_bp, "step": sum(len(it.trials) for it in timed)},
         "mean_backtracks": float(np.mean([it.backtracks for it in timed])),
     }
     if not args.no_time_to_rmse:

@@ -186,6 +186,11 @@ enum {
     FBL_K_COUNT = 6
 };
 FBL_API int fbl_timing_enable(fbl_plan *plan, int on);
+/* Which kernels are bracketed while timing is enabled: bit k of mask selects FBL_K_k
+ * (default: all).  Every bracketed launch adds two event records to its stream, so a
+ * caller that times a whole run selects only the kernels it needs.  Bits at or above
+ * FBL_K_COUNT are FBL_E_INVALID. */
+FBL_API int fbl_timing_select(fbl_plan *plan, uint32_t mask);
 FBL_API int fbl_timing_read(fbl_plan *plan, double ms[FBL_K_COUNT], int64_t launches[FBL_K_COUNT]);
 
 /* fb_lisa_step with stochastic rounding of the trial point to the storage type (for 16-bit

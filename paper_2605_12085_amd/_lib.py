@@ -25,7 +25,8 @@ _PROJ_DTYPES = {"f32": (FBL_F32, torch.float32), "bf16": (FBL_BF16, torch.bfloat
 
 EXPORTED = ("fbl_geometry_check", "fbl_plan_create", "fbl_plan_destroy", "fb_lisa_forward",
             "fb_lisa_backproject", "fb_lisa_step", "fb_lisa_step_sr", "fbl_mlp_workspace_bytes", "fbl_mlp_forward",
-            "fbl_mlp_loss_grad", "fbl_mlp_adam", "fbl_timing_enable", "fbl_timing_read", "fbl_last_error")
+            "fbl_mlp_loss_grad", "fbl_mlp_adam", "fbl_timing_enable", "fbl_timing_select", "fbl_timing_read",
+            "fbl_last_error")
 MLP_IN, MLP_HIDDEN = 5, 64
 MLP_NPARAMS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 KERNELS = ("forward", "transpose", "finalize", "prescale", "backproject", "step")  # FBL_K_* order
@@ -69,12 +70,13 @@ def _load() -> ctypes.CDLL:
     lib.fbl_mlp_adam.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, P]
     lib.fbl_timing_enable.argtypes = [P, ctypes.c_int]
+    lib.fbl_timing_select.argtypes = [P, ctypes.c_uint32]
     lib.fbl_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.fbl_last_error.argtypes = []
     lib.fbl_last_error.restype = ctypes.c_char_p
     for name in ("fbl_geometry_check", "fbl_plan_create", "fb_lisa_forward", "fb_lisa_backproject",
                  "fb_lisa_step", "fb_lisa_step_sr", "fbl_mlp_forward", "fbl_mlp_loss_grad", "fbl_mlp_adam", "fbl_timing_enable",
-                 "fbl_timing_read"):
+                 "fbl_timing_select", "fbl_timing_read"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -165,8 +167,11 @@ class Plan:
         except Exception:
             pass
 
-    def timing(self, on: bool = True) -> None:
-        """Start (and clear) or stop per-launch event timing inside the library."""
+    def timing(self, on: bool = True, kernels: Optional[Sequence[str]] = None) -> None:
+        """Start (and clear) or stop per-launch event timing inside the library; ``kernels``
+        (names from KERNELS) limits the bracketed launches, default all."""
+        mask = (1 << len(KERNELS)) - 1 if kernels is None else sum(1 << KERNELS.index(k) for k in set(kernels))
+        _check(lib.fbl_timing_select(self.handle, mask))
         _check(lib.fbl_timing_enable(self.handle, 1 if on else 0))
 
     def timing_read(self) -> dict:

@@ -95,6 +95,7 @@ struct fbl_plan {
         hipEvent_t start, stop;
     };
     bool timing_on;
+    uint32_t timing_mask;         // bit k: launches of kernel FBL_K_k are bracketed
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
 };

@@ -205,7 +205,7 @@ hipError_t pooled_event(fbl_plan *p, hipEvent_t *ev)
 template <typename F>
 hipError_t timed(fbl_plan *p, int kernel, hipStream_t st, F &&launch)
 {
-    if (!p->timing_on) return launch();
+    if (!p->timing_on || !((p->timing_mask >> kernel) & 1u)) return launch();
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = pooled_event(p, &a);
     if (e == hipSuccess) e = pooled_event(p, &b);
@@ -280,6 +280,7 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
         return fail(FBL_E_RANGE, "max_batch %d outside [1, n_views=%lld]", (int)max_batch, (long long)g->n_views);
 
     fbl_plan *p = new fbl_plan();
+    p->timing_mask = (1u << FBL_K_COUNT) - 1u;
     std::memset((void *)p, 0, sizeof *p);
     p->device = -1;
     hipError_t e = hipGetDevice(&p->device);
@@ -617,6 +618,14 @@ int fbl_timing_enable(fbl_plan *p, int on)
         if (rc != FBL_OK) return rc;
     }
     p->timing_on = on != 0;
+    return ok();
+}
+
+int fbl_timing_select(fbl_plan *p, uint32_t mask)
+{
+    if (!p) return fail(FBL_E_INVALID, "plan is NULL");
+    if (mask >> FBL_K_COUNT) return fail(FBL_E_INVALID, "mask 0x%x has bits beyond FBL_K_COUNT", (unsigned)mask);
+    p->timing_mask = mask;
     return ok();
 }
 

@@ -79,6 +79,7 @@ def test_null_arguments_fail_before_any_device_work():
     assert b"plan" in lib.fbl_last_error()
     assert lib.fb_lisa_backproject(None, None, views, 1, 1.0, None, None) == _lib.FBL_E_INVALID
     assert lib.fb_lisa_step(None, None, None, 1.0, 0.0, 0.0, math.inf, None, None, None) == _lib.FBL_E_INVALID
+    assert lib.fbl_timing_select(None, 1) == _lib.FBL_E_INVALID
     assert lib.fbl_plan_create(None, 0, 0, 1, None) == _lib.FBL_E_INVALID
     out = ctypes.c_void_p(1)
     assert lib.fbl_plan_create(None, 0, 0, 1, ctypes.byref(out)) == _lib.FBL_E_INVALID

@@ -304,6 +304,15 @@ def test_launch_timing_records_every_kernel(fbl):
         plan.timing(False)
         fbl.fb_lisa_forward(plan, x, views)
         assert all(n == 0 for _, n in plan.timing_read().values())
+        # a selection brackets only the chosen kernels
+        plan.timing(True, kernels=("forward", "backproject"))
+        r = fbl.fb_lisa_forward(plan, x, views, b, loss=loss)
+        fbl.fb_lisa_backproject(plan, r, views)
+        fbl.fb_lisa_step(plan, x, gr, 1e-3)
+        kt = plan.timing_read()
+        assert {k: n for k, (_, n) in kt.items()} == {"forward": 1, "transpose": 0, "finalize": 0, "prescale": 0,
+                                                       "backproject": 1, "step": 0}
+        plan.timing(False)
         torch.cuda.synchronize()
 
 
