@@ -88,7 +88,7 @@ struct fbl_plan {
     int fp_blocks_per_view;       // forward launch shape
     int fp_line;                  // per-thread LDS line length of the forward
     int bp_pairs;                 // detector columns per slice the backprojection tile holds
-    int bp_cand;                  // detector rows examined per voxel in the z-profile gather
+    int bp_cand;                  // detector rows that can reach one voxel on a slice (the fallback tap loop)
     // launch timing (off unless fbl_timing_enable): event pairs around each launch
     struct TimedLaunch {
         int kernel;
