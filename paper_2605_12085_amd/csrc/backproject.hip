@@ -316,7 +316,8 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                     for (int j = 0; j < kSegRows; ++j) {
                         const int q = fin ? (int)rintf(ldexpf(wv[cs][j], kx)) : 0;
                         P += q;
-                        Q += (wseg * kSegRows + j - kRowCen) * q;
+                        // |row - kRowCen| <= 14 and |q| <= 2^22 both fit 24 bits: a 24-bit product
+                        Q += __mul24(wseg * kSegRows + j - kRowCen, q);
                         ps[j] = P;
                         qs[j] = Q;
                     }
