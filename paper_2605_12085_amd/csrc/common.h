@@ -85,7 +85,7 @@ struct fbl_plan {
     float *d_rw;                  // [max_batch][nv][nu] weighted residual for the backprojection
     void *d_xt;                   // [nz][nx][ny] y-fastest copy of the forward's input volume
     unsigned char *view_axis0;    // host, per view: 1 if some column marches x = const slices
-    int fp_blocks_per_view;       // forward launch shape
+    int fp_blocks_max;            // forward blocks per view at the finest split (partials sizing)
     int fp_line;                  // per-thread LDS line length of the forward
     int bp_pairs;                 // detector columns per slice the backprojection tile holds
     int bp_cand;                  // detector rows that can reach one voxel on a slice (the fallback tap loop)
@@ -105,9 +105,11 @@ namespace fbl {
 // Launch functions (stream-ordered, no synchronisation).  Each returns hipSuccess or the
 // launch error.
 hipError_t launch_transpose(const fbl_plan *p, const void *x, hipStream_t st);
+// parts: the slice march of each ray split over 1, 2 or 4 waves (forward_parts).
 hipError_t launch_forward(const fbl_plan *p, const void *x, const ViewList &vl, int nb, int first,
-                          const void *b, float *y, bool want_loss, hipStream_t st);
-int forward_blocks_per_view(const Geo &g);
+                          const void *b, float *y, bool want_loss, int parts, hipStream_t st);
+int forward_blocks_per_view(const Geo &g, int parts);
+int forward_parts(const Geo &g, int B);   // parts for a call of B views (fills the chip)
 int forward_rows_per_thread();
 hipError_t launch_finalize_sum(double *partials, int64_t n, int ncomp, double scale, double *out,
                                hipStream_t st);

@@ -13,6 +13,9 @@
 //     reads its two vertical taps with one ds_read2st64 and does one lerp.
 //   - Ray positions are refreshed in FP64 every kChunk slices and stepped in FP32
 //     inside the chunk; per-chunk FP32 partial sums keep the 256-1024-term sums accurate.
+//   - When a launch has too few rays to fill the chip, the waves of a block split the
+//     slice march of the same rays (PARTS parts of whole chunks) and add their sums in a
+//     fixed order at the end.
 #include "common.h"
 #include "device_util.h"
 
@@ -25,6 +28,7 @@ constexpr int kWaves = 4;     // row groups per block (one per wavefront)
 constexpr int kRows = 16;     // rays (rows) per thread
 constexpr int kChunk = 16;    // slices per FP64 position refresh and per FP32 partial sum
 constexpr int kThreads = kCols * kWaves;
+constexpr int kFillWaves = 2048;  // two waves per SIMD: below this a launch splits the slice march
 
 // Horizontal pair of taps (p, p+1) of one z-row: both at consecutive addresses.
 template <typename TV>
@@ -52,7 +56,9 @@ struct LineRegs {
 // Waves per SIMD the register budget is held to: short lines fit four (<= 128 VGPRs).
 constexpr int fp_waves(int kb) { return kb <= 16 ? 4 : kb <= 32 ? 3 : 2; }
 
-template <typename TV, typename TB, int KB>
+// PARTS: parts of the slice march per ray (the block's waves are kWaves / PARTS row
+// groups of PARTS parts each).
+template <typename TV, typename TB, int KB, int PARTS>
 __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
     const TV *__restrict__ x, const TV *__restrict__ xt, Geo geo, DeviceTables tab, ViewList vl, int first,
     const TB *__restrict__ b, float *__restrict__ y, double *__restrict__ partials, int blocks_per_view,
@@ -65,8 +71,12 @@ __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
     const int tiles_u = (geo.nu + kCols - 1) / kCols;
     const int tid = threadIdx.x;
     const int lane = tid & (kCols - 1), wave = tid / kCols;
+    constexpr int kGroups = kWaves / PARTS;
+    static_assert(kGroups * PARTS == kWaves, "PARTS divides the waves of a block");
+    static_assert((PARTS - 1) * kGroups * kRows * kCols <= KB * kThreads, "the line buffer holds the parts' sums");
+    const int grp = wave % kGroups, part = wave / kGroups;
     const int c = (blockIdx.x % tiles_u) * kCols + lane;
-    const int r0 = ((blockIdx.x / tiles_u) * kWaves + wave) * kRows;
+    const int r0 = ((blockIdx.x / tiles_u) * kGroups + grp) * kRows;
     const int nrows = max(0, min(kRows, geo.nv - r0));
     const bool active = c < geo.nu && nrows > 0;
 
@@ -97,8 +107,12 @@ __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
     int na_max = na;
     for (int off = 32; off > 0; off >>= 1) na_max = max(na_max, __shfl_xor(na_max, off, 64));
 
-    for (int m0 = 0; m0 < na_max; m0 += kChunk) {
-        const int sc = min(kChunk, na - m0);   // slices of this lane in the chunk (may be <= 0)
+    // this wave's part of the march: whole chunks [mb, mb + seg) (the wave's columns, and
+    // with them na_max, are the same in every part)
+    const int seg = ((na_max + PARTS - 1) / PARTS + kChunk - 1) / kChunk * kChunk;
+    const int mb = part * seg, me = min(na, mb + seg);
+    for (int m0 = mb; m0 < min(na_max, mb + seg); m0 += kChunk) {
+        const int sc = min(kChunk, me - m0);   // slices of this lane in the chunk (may be <= 0)
         // FP64 positions at the chunk's first slice.  Integer bases are taken below the
         // smallest value reached in the chunk, so all in-chunk offsets are >= 0 and
         // truncation equals floor.
@@ -200,8 +214,25 @@ __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
         for (int r = 0; r < kRows; ++r) acc[r] += part[r];
     }
 
+    if constexpr (PARTS > 1) {
+        // parts 1..S-1 hand their sums to part 0 through the line buffer
+        __syncthreads();
+        float *__restrict__ xfer = line;
+        if (part > 0) {
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) xfer[(((part - 1) * kGroups + grp) * kRows + r) * kCols + lane] = acc[r];
+        }
+        __syncthreads();
+        if (part == 0) {
+#pragma unroll
+            for (int q = 1; q < PARTS; ++q) {
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) acc[r] += xfer[(((q - 1) * kGroups + grp) * kRows + r) * kCols + lane];
+            }
+        }
+    }
     double sq = 0.0;
-    if (active) {
+    if (active && part == 0) {
         const int64_t row0 = (int64_t)(first + bi) * geo.np;
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
@@ -259,22 +290,42 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double *__restrict_
 
 }  // namespace
 
-int forward_blocks_per_view(const Geo &g)
+int forward_blocks_per_view(const Geo &g, int parts)
 {
-    return ((g.nu + kCols - 1) / kCols) * ((g.nv + kWaves * kRows - 1) / (kWaves * kRows));
+    const int rows = (kWaves / parts) * kRows;
+    return ((g.nu + kCols - 1) / kCols) * ((g.nv + rows - 1) / rows);
+}
+
+int forward_parts(const Geo &g, int B)
+{
+    for (int parts = 1; parts < kWaves; parts *= 2)
+        if ((int64_t)kWaves * forward_blocks_per_view(g, parts) * B >= kFillWaves) return parts;
+    return kWaves;
 }
 
 int forward_rows_per_thread() { return kRows; }
 
-template <typename TV, typename TB, int KB>
-static hipError_t launch_fp_kb(const fbl_plan *p, const void *x, const void *xt, const ViewList &vl, int nb,
-                               int first, const void *b, float *y, bool want_loss, hipStream_t st)
+template <typename TV, typename TB, int KB, int S>
+static hipError_t launch_fp_s(const fbl_plan *p, const void *x, const void *xt, const ViewList &vl, int nb,
+                              int first, const void *b, float *y, bool want_loss, hipStream_t st)
 {
     DeviceTables tab{p->d_col, p->d_rowV, p->d_rowV2, p->d_view};
-    dim3 grid(p->fp_blocks_per_view, nb);
-    hipLaunchKernelGGL((fp_kernel<TV, TB, KB>), grid, dim3(kThreads), 0, st, (const TV *)x, (const TV *)xt, p->geo,
-                       tab, vl, first, (const TB *)b, y, p->d_partials, p->fp_blocks_per_view, want_loss ? 1 : 0);
+    const int bpv = forward_blocks_per_view(p->geo, S);
+    dim3 grid(bpv, nb);
+    hipLaunchKernelGGL((fp_kernel<TV, TB, KB, S>), grid, dim3(kThreads), 0, st, (const TV *)x, (const TV *)xt,
+                       p->geo, tab, vl, first, (const TB *)b, y, p->d_partials, bpv, want_loss ? 1 : 0);
     return hipGetLastError();
+}
+
+template <typename TV, typename TB, int KB>
+static hipError_t launch_fp_kb(const fbl_plan *p, const void *x, const void *xt, const ViewList &vl, int nb,
+                               int first, const void *b, float *y, bool want_loss, int parts, hipStream_t st)
+{
+    switch (parts) {
+    case 1: return launch_fp_s<TV, TB, KB, 1>(p, x, xt, vl, nb, first, b, y, want_loss, st);
+    case 2: return launch_fp_s<TV, TB, KB, 2>(p, x, xt, vl, nb, first, b, y, want_loss, st);
+    default: return launch_fp_s<TV, TB, KB, 4>(p, x, xt, vl, nb, first, b, y, want_loss, st);
+    }
 }
 
 template <typename TV>
@@ -297,36 +348,36 @@ hipError_t launch_transpose(const fbl_plan *p, const void *x, hipStream_t st)
 
 template <typename TV, typename TB>
 static hipError_t launch_fp_t(const fbl_plan *p, const void *x, const ViewList &vl, int nb, int first,
-                              const void *b, float *y, bool want_loss, hipStream_t st)
+                              const void *b, float *y, bool want_loss, int parts, hipStream_t st)
 {
     const void *xt = p->d_xt;
     switch (p->fp_line) {
-    case 12: return launch_fp_kb<TV, TB, 12>(p, x, xt, vl, nb, first, b, y, want_loss, st);
-    case 16: return launch_fp_kb<TV, TB, 16>(p, x, xt, vl, nb, first, b, y, want_loss, st);
-    case 24: return launch_fp_kb<TV, TB, 24>(p, x, xt, vl, nb, first, b, y, want_loss, st);
-    case 32: return launch_fp_kb<TV, TB, 32>(p, x, xt, vl, nb, first, b, y, want_loss, st);
-    default: return launch_fp_kb<TV, TB, 48>(p, x, xt, vl, nb, first, b, y, want_loss, st);
+    case 12: return launch_fp_kb<TV, TB, 12>(p, x, xt, vl, nb, first, b, y, want_loss, parts, st);
+    case 16: return launch_fp_kb<TV, TB, 16>(p, x, xt, vl, nb, first, b, y, want_loss, parts, st);
+    case 24: return launch_fp_kb<TV, TB, 24>(p, x, xt, vl, nb, first, b, y, want_loss, parts, st);
+    case 32: return launch_fp_kb<TV, TB, 32>(p, x, xt, vl, nb, first, b, y, want_loss, parts, st);
+    default: return launch_fp_kb<TV, TB, 48>(p, x, xt, vl, nb, first, b, y, want_loss, parts, st);
     }
 }
 
 template <typename TV>
 static hipError_t launch_fp_b(const fbl_plan *p, const void *x, const ViewList &vl, int nb, int first,
-                              const void *b, float *y, bool want_loss, hipStream_t st)
+                              const void *b, float *y, bool want_loss, int parts, hipStream_t st)
 {
     switch (p->proj_dtype) {
-    case FBL_F32: return launch_fp_t<TV, float>(p, x, vl, nb, first, b, y, want_loss, st);
-    case FBL_BF16: return launch_fp_t<TV, __hip_bfloat16>(p, x, vl, nb, first, b, y, want_loss, st);
-    default: return launch_fp_t<TV, __half>(p, x, vl, nb, first, b, y, want_loss, st);
+    case FBL_F32: return launch_fp_t<TV, float>(p, x, vl, nb, first, b, y, want_loss, parts, st);
+    case FBL_BF16: return launch_fp_t<TV, __hip_bfloat16>(p, x, vl, nb, first, b, y, want_loss, parts, st);
+    default: return launch_fp_t<TV, __half>(p, x, vl, nb, first, b, y, want_loss, parts, st);
     }
 }
 
 hipError_t launch_forward(const fbl_plan *p, const void *x, const ViewList &vl, int nb, int first, const void *b,
-                          float *y, bool want_loss, hipStream_t st)
+                          float *y, bool want_loss, int parts, hipStream_t st)
 {
     switch (p->vol_dtype) {
-    case FBL_F32: return launch_fp_b<float>(p, x, vl, nb, first, b, y, want_loss, st);
-    case FBL_BF16: return launch_fp_b<__hip_bfloat16>(p, x, vl, nb, first, b, y, want_loss, st);
-    default: return launch_fp_b<__half>(p, x, vl, nb, first, b, y, want_loss, st);
+    case FBL_F32: return launch_fp_b<float>(p, x, vl, nb, first, b, y, want_loss, parts, st);
+    case FBL_BF16: return launch_fp_b<__hip_bfloat16>(p, x, vl, nb, first, b, y, want_loss, parts, st);
+    default: return launch_fp_b<__half>(p, x, vl, nb, first, b, y, want_loss, parts, st);
     }
 }
 

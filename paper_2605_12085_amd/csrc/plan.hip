@@ -471,8 +471,8 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
         std::stable_sort(bp_order.begin(), bp_order.end(),
                          [&](int a, int b) { return r2[(size_t)(a % (tx * ty))] < r2[(size_t)(b % (tx * ty))]; });
     }
-    p->fp_blocks_per_view = forward_blocks_per_view(G);
-    const int64_t np_fp = (int64_t)max_batch * p->fp_blocks_per_view;
+    p->fp_blocks_max = forward_blocks_per_view(G, 4);
+    const int64_t np_fp = (int64_t)max_batch * p->fp_blocks_max;
     const int64_t np_step = 3 * (int64_t)step_blocks(p);
     p->n_partials = np_fp > np_step ? np_fp : np_step;
 
@@ -515,15 +515,17 @@ int fb_lisa_forward(fbl_plan *p, const void *x, const int32_t *views, int32_t B,
         hipError_t e = timed(p, FBL_K_TRANSPOSE, st, [&] { return launch_transpose(p, x, st); });
         if (e != hipSuccess) return hip_fail(e, "volume transpose launch");
     }
+    const int parts = forward_parts(p->geo, B);
     for (int first = 0; first < B; first += kViewsPerLaunch) {
         const int nb = B - first < kViewsPerLaunch ? B - first : kViewsPerLaunch;
         const ViewList vl = chunk(views, first, nb);
-        hipError_t e = timed(p, FBL_K_FORWARD, st,
-                             [&] { return launch_forward(p, x, vl, nb, first, b, y, loss_dev != nullptr, st); });
+        hipError_t e = timed(p, FBL_K_FORWARD, st, [&] {
+            return launch_forward(p, x, vl, nb, first, b, y, loss_dev != nullptr, parts, st);
+        });
         if (e != hipSuccess) return hip_fail(e, "forward projection launch");
     }
     if (loss_dev) {
-        const int64_t n = (int64_t)B * p->fp_blocks_per_view;
+        const int64_t n = (int64_t)B * forward_blocks_per_view(p->geo, parts);
         hipError_t e = timed(p, FBL_K_FINALIZE, st,
                              [&] { return launch_finalize_sum(p->d_partials, n, 1, loss_scale, loss_dev, st); });
         if (e != hipSuccess) return hip_fail(e, "loss reduction launch");
