@@ -253,27 +253,39 @@ __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
 }
 
 // xt[k][i][j] = x[k][j][i]: y-fastest copy read by views whose slices are x = const.
+// A block moves a 32 x 32 tile of kTrZ consecutive z-slices: every load is issued before
+// the first store, and each block moves kTrZ times 4 KB (FP32).
+constexpr int kTrZ = 4;
 template <typename TV>
 __global__ __launch_bounds__(256) void transpose_xy_kernel(const TV *__restrict__ x, TV *__restrict__ xt, int nx,
                                                            int ny, int nz)
 {
-    __shared__ TV tile[32][33];
+    __shared__ TV tile[kTrZ][32][33];
     const int tiles_x = (nx + 31) / 32;
     const int ti = blockIdx.x % tiles_x, tj = blockIdx.x / tiles_x;
-    const int k = blockIdx.y;
+    const int k0 = blockIdx.y * kTrZ;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-    const int64_t slab = (int64_t)k * nx * ny;
+    const int64_t plane = (int64_t)nx * ny;
+    TV v[kTrZ][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int j = tj * 32 + ty + 8 * q, i = ti * 32 + tx;
-        if (i < nx && j < ny) tile[ty + 8 * q][tx] = x[slab + (int64_t)j * nx + i];
-    }
+    for (int z = 0; z < kTrZ; ++z)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = tj * 32 + ty + 8 * q, i = ti * 32 + tx;
+            if (i < nx && j < ny && k0 + z < nz) v[z][q] = x[(int64_t)(k0 + z) * plane + (int64_t)j * nx + i];
+        }
+#pragma unroll
+    for (int z = 0; z < kTrZ; ++z)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tile[z][ty + 8 * q][tx] = v[z][q];
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int i = ti * 32 + ty + 8 * q, j = tj * 32 + tx;
-        if (i < nx && j < ny) xt[slab + (int64_t)i * ny + j] = tile[tx][ty + 8 * q];
-    }
+    for (int z = 0; z < kTrZ; ++z)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = ti * 32 + ty + 8 * q, j = tj * 32 + tx;
+            if (i < nx && j < ny && k0 + z < nz) xt[(int64_t)(k0 + z) * plane + (int64_t)i * ny + j] = tile[z][tx][ty + 8 * q];
+        }
 }
 
 __global__ __launch_bounds__(256) void finalize_kernel(const double *__restrict__ partials, int64_t n, int ncomp,
@@ -332,7 +344,7 @@ template <typename TV>
 static hipError_t launch_transpose_t(const fbl_plan *p, const void *x, hipStream_t st)
 {
     const int tiles = ((p->geo.nx + 31) / 32) * ((p->geo.ny + 31) / 32);
-    hipLaunchKernelGGL((transpose_xy_kernel<TV>), dim3(tiles, p->geo.nz), dim3(256), 0, st, (const TV *)x,
+    hipLaunchKernelGGL((transpose_xy_kernel<TV>), dim3(tiles, (p->geo.nz + kTrZ - 1) / kTrZ), dim3(256), 0, st, (const TV *)x,
                        (TV *)p->d_xt, p->geo.nx, p->geo.ny, p->geo.nz);
     return hipGetLastError();
 }
