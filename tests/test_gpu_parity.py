@@ -171,6 +171,43 @@ def test_backproject_wide_dynamic_range(fbl, orc):
     _cmp_vol(gg, ref, what="backprojection, wide dynamic range")
 
 
+def test_fine_detector_columns_wide_pair_tables(fbl, orc):
+    # detector columns 0.7 voxel apart at the detector (about 0.35 voxel at the volume):
+    # up to 55 columns cross one 16-voxel tile slice, so the backprojection takes its
+    # 64-column pair tables (two blocks per compute unit)
+    g = syn.Geometry(24, 24, 20, 1.0, 1.0, 1.0, 77, 30, 0.7, 1.5, 300.0, 600.0, 8)
+    rng = np.random.default_rng(17)
+    views = np.arange(g.n_views, dtype=np.int32)
+    x = rng.uniform(0, 1, g.vol_shape).astype(np.float32)
+    r = rng.standard_normal((len(views), g.nv, g.nu)).astype(np.float32)
+    y_ref = orc.forward(g, x.astype(np.float64), views)
+    g_ref = orc.backproject(g, r.astype(np.float64), views)
+    with fbl.Plan(g) as plan:
+        y = fbl.fb_lisa_forward(plan, _t(x), views).cpu().numpy()
+        gg = fbl.fb_lisa_backproject(plan, _t(r), views, grad_scale=1.0).cpu().numpy()
+    _cmp_views(y, y_ref, what="forward fine columns")
+    _cmp_vol(gg, g_ref, what="backprojection fine columns")
+
+
+def test_forward_split_march_two_parts(fbl, orc):
+    # 40 views of the 128^3 / 192^2 workload: one march part per ray would give 1440
+    # waves, under two per SIMD, so the forward splits each ray's march over two waves
+    g = syn.config_geometry("c4")
+    cfg = syn.CONFIGS["c4"]
+    ells, xt = syn.phantom(g, cfg["k"], seed=41, hi=cfg["hi"])
+    views = syn.view_permutations(g.n_views, 1, seed=42)[0][:40]
+    b = syn.add_noise(syn.ellipsoid_line_integrals(g, ells, np.arange(g.n_views)), 0.01, seed=43).astype(np.float32)
+    x = (0.8 * xt).astype(np.float32)
+    y_ref = orc.forward(g, x.astype(np.float64), views) - b[views].astype(np.float64)
+    f_ref = g.n_views / (2.0 * len(views)) * float(np.sum(y_ref ** 2))
+    import torch
+    with fbl.Plan(g, max_batch=40) as plan:
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        y = fbl.fb_lisa_forward(plan, _t(x), views, _t(b), loss=loss).cpu().numpy()
+    _cmp_views(y, y_ref, what="forward, split march")
+    assert float(loss) == pytest.approx(f_ref, rel=TOL)
+
+
 def test_adjoint_identity_on_gpu(fbl):
     import torch
     g = syn.Geometry(40, 36, 30, 1.0, 1.0, 1.0, 60, 44, 1.4, 1.4, 400.0, 800.0, 16)
