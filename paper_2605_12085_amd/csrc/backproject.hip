@@ -49,8 +49,8 @@ namespace {
 constexpr int kTQ = 16;        // tile extent along x and along y (and slices per class pass)
 constexpr int kTK = 16;        // tile extent along z (voxels per thread)
 constexpr int kKH = 8;         // z-entries per half pass
-constexpr int kKQ = 4;         // z-entries per profile work item
-static_assert(kKH == 2 * kKQ, "a half pass has two profile items per pair");
+constexpr int kKQ = 4;         // z-entries per work item of the fallback tap loop
+static_assert(kKH == 2 * kKQ, "the fallback tap loop has two items per pair and half pass");
 constexpr int kThreads = 256;
 constexpr int kWinRows = 28;   // staged rows per column (longer spans read global memory)
 constexpr int kSegRows = kWinRows / 4;     // rows per lane: four lanes share a column
