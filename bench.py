@@ -19,6 +19,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import re
 import math
 import os
 import sys
@@ -41,10 +42,15 @@ KERNEL_SOURCES = {"fp_kernel": "forward.hip", "bp_kernel": "backproject.hip"}
 
 
 def kernel_source_hash(kernel: str) -> str:
+    """Hash of a kernel's source and its device helpers, comments and spacing removed, so
+    that a counter summary stays valid across edits that change no code."""
     h = hashlib.sha256()
     for f in (KERNEL_SOURCES[kernel], "device_util.h"):
-        with open(os.path.join(ROOT, "paper_2605_12085_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2605_12085_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
