@@ -125,17 +125,19 @@ class StepModel:
 
 class LearnedStep:
     """Proposer for FBLisa.run(alpha_init=...): alpha_0 at the first iteration, then
-    alpha_0 * beta^j with j the predicted number of halvings rounded down and clipped to
-    [0, j_max] -- a proposal on the method's own step grid, never above alpha_0.
+    alpha_0 * beta^j with j the predicted number of halvings rounded down, less `margin`,
+    clipped to [0, j_max] -- a proposal on the method's own step grid, never above alpha_0.
 
-    Rounding down errs towards the larger step: a proposal above the step the plain
-    search would accept costs one more trial (one forward projection) and then lands on
-    that same step, while a proposal below it is accepted as is and shortens the step,
-    which costs iterations."""
+    The proposal errs towards the larger step: one above the step the plain search would
+    accept costs one more trial (one forward projection) and then lands on that same step,
+    while one below it is accepted as is and shortens the step, which costs iterations.
+    margin = 1 proposes one notch larger still: the run then follows the plain search's
+    steps more closely, at the price of more trials."""
 
-    def __init__(self, model: StepModel, j_max: int = 20):
+    def __init__(self, model: StepModel, j_max: int = 20, margin: int = 0):
         self.model = model
         self.j_max = j_max
+        self.margin = int(margin)
         dev = model.params.device
         self._x = torch.empty((1, MLP_IN), dtype=torch.float32).pin_memory()
         self._xd = torch.empty((1, MLP_IN), dtype=torch.float32, device=dev)
@@ -152,6 +154,6 @@ class LearnedStep:
         self._y.copy_(self._yd, non_blocking=True)
         torch.cuda.current_stream().synchronize()
         log_ratio = float(self._y[0])
-        j = int(math.floor(log_ratio / math.log10(run.beta))) if math.isfinite(log_ratio) else 0
+        j = int(math.floor(log_ratio / math.log10(run.beta))) - self.margin if math.isfinite(log_ratio) else 0
         j = min(max(j, 0), self.j_max)
         return run.alpha0 * run.beta ** j
