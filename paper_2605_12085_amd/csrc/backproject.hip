@@ -182,6 +182,11 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
             const int na = axis == 0 ? geo.nx : geo.ny;
             const int mt0 = axis == 0 ? i0 : j0;       // first slice of the tile
             const int q0 = axis == 0 ? j0 : i0;        // first in-slice index of the tile
+            // The class's outermost columns, read before the slices' column ranges are known
+            // so that the loads overlap that step and its barrier.  Every pair of the class
+            // lies within [cl0, cl1], and its ray parameter is monotone along a detector row,
+            // so bounds taken at these two columns hold for all of its pairs.
+            const ColParam ca = cols[cl0], cb = cols[cl1];
             __syncthreads();   // the previous class's readers are done with the shared arrays
             // 1. per-slice column ranges (lanes 0..15 of wave 0), each slice's first pair (a
             //    prefix sum over those lanes) and the class window's columns [c0, c1], the
@@ -233,16 +238,15 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
             const int c0 = cspan[0], c1 = cspan[1], NP = cspan[2];
             if (c1 < 0) continue;   // uniform across the block
             const int nC = c1 - c0 + 1;
-            // extremes of the ray parameter over the class's pairs: tau is monotone along
-            // a detector row (inversely proportional to the column's D_a, which is affine
-            // in the column) and affine in the slice, so they sit at the corner (first/last
-            // column, first/last slice) pairs; a detector row of a given height is monotone
-            // in tau.  Bounds are taken in FP32 with the hardware reciprocal (rounding is far
+            // bounds of the ray parameter over the class's pairs: tau is monotone along a
+            // detector row (inversely proportional to the column's D_a, which is affine in
+            // the column) and affine in the slice, so over columns [cl0, cl1] and the tile's
+            // slices they sit at the corners; a detector row of a given height is monotone in
+            // tau.  Bounds are taken in FP32 with the hardware reciprocal (rounding is far
             // below the one-row margins).
             float imin, imax;
             {
                 const int mA = mt0, mB = min(mt0 + kTQ - 1, na - 1);
-                const ColParam ca = cols[c0], cb = cols[c1];
                 const double t00 = fma((double)mA, ca.t1, ca.t0), t01 = fma((double)mB, ca.t1, ca.t0);
                 const double t10 = fma((double)mA, cb.t1, cb.t0), t11 = fma((double)mB, cb.t1, cb.t0);
                 imin = __builtin_amdgcn_rcpf((float)(fmax(fmax(t00, t01), fmax(t10, t11)) * dvz));
