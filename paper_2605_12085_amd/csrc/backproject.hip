@@ -137,8 +137,6 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
     __shared__ short pcr[NPM];                        // the pair's column minus the class window's c0
     __shared__ int2 pre[kWinCols * kPreStride];       // per window column and T: (P(T), Q(T)), integers
     __shared__ int pexp[kWinCols];                    // per window column: residual scale exponent
-    __shared__ int colA[kTQ], colN[kTQ], pfx[kTQ];    // per slice: first column, count, first pair
-    __shared__ int cspan[3];                          // the class window's first and last column, pair count
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -188,10 +186,13 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
             // so bounds taken at these two columns hold for all of its pairs.
             const ColParam ca = cols[cl0], cb = cols[cl1];
             __syncthreads();   // the previous class's readers are done with the shared arrays
-            // 1. per-slice column ranges (lanes 0..15 of wave 0), each slice's first pair (a
-            //    prefix sum over those lanes) and the class window's columns [c0, c1], the
-            //    union of the slices' ranges (a reduction over them), by lane exchanges
-            if (wave == 0) {
+            // 1. per-slice column ranges in lanes 0..15 of every wave, each slice's first pair
+            //    (a prefix sum over those lanes) and the class window's columns [c0, c1], the
+            //    union of the slices' ranges (a reduction over them), by lane exchanges.  Every
+            //    wave computes the same values from the same inputs and keeps them in its own
+            //    registers, read by lane index where needed, so none pass through LDS.
+            int sa, sn, sp, c0, c1, NP;
+            {
                 const int mg = mt0 + lane;
                 int a = 0, n = 0;
                 if (lane < kTQ && mg < na) {
@@ -223,19 +224,13 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                     lo = min(lo, __shfl_xor(lo, off));
                     hi = max(hi, __shfl_xor(hi, off));
                 }
-                if (lane < kTQ) {
-                    colA[lane] = a;
-                    colN[lane] = n;
-                    pfx[lane] = incl - n;
-                }
-                if (lane == kTQ - 1) {
-                    cspan[0] = lo;
-                    cspan[1] = hi;
-                    cspan[2] = incl;
-                }
+                sa = a;
+                sn = n;
+                sp = incl - n;
+                c0 = __shfl(lo, 0);
+                c1 = __shfl(hi, 0);
+                NP = __shfl(incl, kTQ - 1);
             }
-            __syncthreads();
-            const int c0 = cspan[0], c1 = cspan[1], NP = cspan[2];
             if (c1 < 0) continue;   // uniform across the block
             const int nC = c1 - c0 + 1;
             // bounds of the ray parameter over the class's pairs: tau is monotone along a
@@ -352,7 +347,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
             // one in every 16 (kPairIters = WP / 16 rounds cover the slice's at most WP).
             static_assert(kThreads == kTQ * 16 && WP % 16 == 0, "16 threads per slice");
             const int sm = tid >> 4, si = tid & 15;
-            const int sA = colA[sm], sN = colN[sm], sF = pfx[sm];
+            const int sA = __shfl(sa, sm), sN = __shfl(sn, sm), sF = __shfl(sp, sm);
             ColParam pc[kPairIters];
 #pragma unroll
             for (int i = 0; i < kPairIters; ++i)
@@ -387,9 +382,9 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
             int gfirst = 0, gcnt = 0;
             {
                 const int m = axis == 0 ? ti : tj;
-                const int n = colN[m];
-                const float *__restrict__ xs = xiq + pfx[m];
-                gfirst = pfx[m];
+                const int n = __shfl(sn, m);
+                gfirst = __shfl(sp, m);
+                const float *__restrict__ xs = xiq + gfirst;
                 if (n > 0) {
                     const float sgn = (n >= 2 && xs[n - 1] < xs[0]) ? -1.0f : 1.0f;
                     // first pair with sgn*xi > sgn*q - 1 (sgn*xi increases along the slice)
