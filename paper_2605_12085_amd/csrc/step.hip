@@ -8,7 +8,36 @@ namespace {
 
 constexpr int kStepBlocks = 2048;   // 8 blocks per compute unit, grid-stride over the volume
 
+// Four consecutive storage values as one 16-byte (FP32) or 8-byte (16-bit) access.
+template <typename TV>
+__device__ __forceinline__ void load4(const TV *__restrict__ p, int64_t q, TV (&v)[4])
+{
+    if constexpr (sizeof(TV) == 4) {
+        const float4 t = reinterpret_cast<const float4 *>(p)[q];
+        __builtin_memcpy(v, &t, sizeof(t));
+    } else {
+        const uint2 t = reinterpret_cast<const uint2 *>(p)[q];
+        __builtin_memcpy(v, &t, sizeof(t));
+    }
+}
+
+template <typename TV>
+__device__ __forceinline__ void store4(TV *__restrict__ p, int64_t q, const TV (&v)[4])
+{
+    if constexpr (sizeof(TV) == 4) {
+        float4 t;
+        __builtin_memcpy(&t, v, sizeof(t));
+        reinterpret_cast<float4 *>(p)[q] = t;
+    } else {
+        uint2 t;
+        __builtin_memcpy(&t, v, sizeof(t));
+        reinterpret_cast<uint2 *>(p)[q] = t;
+    }
+}
+
 // SR: round the trial point stochastically (counter-based, keyed) instead of to nearest.
+// Each thread takes four consecutive voxels per pass (one wide access per array), then
+// the last d mod 4 voxels one by one.
 template <typename TV, bool SR>
 __global__ __launch_bounds__(256) void step_kernel(const TV *__restrict__ x, const float *__restrict__ g,
                                                    double alpha, double amu, double lo, double hi, uint64_t key,
@@ -19,18 +48,31 @@ __global__ __launch_bounds__(256) void step_kernel(const TV *__restrict__ x, con
 #pragma clang fp contract(off)
     __shared__ double red[4];
     double s_inner = 0.0, s_sq = 0.0, s_gg = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d; i += (int64_t)gridDim.x * 256) {
-        const double xv = (double)to_f32(x[i]);
-        const double gv = (double)g[i];
+    auto trial = [&](float xf, float gf, int64_t i) -> TV {
+        const double xv = (double)xf;
+        const double gv = (double)gf;
         double v = (xv - alpha * gv) - amu;
         v = fmin(fmax(v, lo), hi);
         const TV out = SR ? round_stochastic<TV>(v, key, (uint64_t)i) : from_f64<TV>(v);
-        xbar[i] = out;
         const double dl = (double)to_f32(out) - xv;
         s_inner += gv * dl;
         s_sq += dl * dl;
         s_gg += gv * gv;
+        return out;
+    };
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    const int64_t d4 = d >> 2;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < d4; q += stride) {
+        TV xv[4], out[4];
+        load4(x, q, xv);
+        const float4 g4 = reinterpret_cast<const float4 *>(g)[q];
+        const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[k] = trial(to_f32(xv[k]), gv[k], 4 * q + k);
+        store4(xbar, q, out);
     }
+    for (int64_t i = 4 * d4 + (int64_t)blockIdx.x * 256 + threadIdx.x; i < d; i += stride)
+        xbar[i] = trial(to_f32(x[i]), g[i], i);
     const double a = block_sum_256(s_inner, red);
     const double b = block_sum_256(s_sq, red);
     const double c = block_sum_256(s_gg, red);
