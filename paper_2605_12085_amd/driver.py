@@ -78,8 +78,8 @@ class FBLisa:
     """GPU FB-LISA on a fixed data set b [n_views][nv][nu] (device tensor).
 
     x starts at x0 (default 0).  ``alpha_init(state)`` may propose the first trial step
-    of an iteration (default: alpha_0, the paper's reset); the backtracking stays the
-    judge of every proposal.
+    of an iteration (default: alpha_0, the paper's reset); the sufficient-decrease test
+    and the backtracking still decide on every proposal.
     """
 
     def __init__(self, geom, b: torch.Tensor, *, n0: int, epochs: int, alpha0: float = 1e-3, beta: float = 0.5,
