@@ -143,7 +143,7 @@ def warm_clock(fbl, plan, x, views, r, g, seconds=None):
         torch.cuda.synchronize()
 
 
-def time_to_rmse(fbl, g, cfg, b32, xt, perms, proposer):
+def time_to_rmse(fbl, g, cfg, b32, xt, perms, proposer, variants=("bf16", "bf16_nearest", "f16", "f32")):
     """Wall time to the reconstruction error of the plain FP32 run: the plain FP32 run sets
     RMSE* (its error after the configured epochs) and is timed to its first iterate at or
     below RMSE*; the learned-step run with BF16 volume and FP16 data storage is timed to
@@ -155,8 +155,10 @@ def time_to_rmse(fbl, g, cfg, b32, xt, perms, proposer):
         pass
 
     def go(b_dev, vol_dtype, alpha_init, target, sr_seed=None):
+        # the constant-batch C keeps N_t = N_0 for the configured epochs, so buffers for
+        # one batch suffice (n_max)
         run = fbl.FBLisa(g, b_dev, n0=cfg["batch"], epochs=cfg["epochs"], lo=cfg["lo"], hi=cfg["hi"],
-                         vol_dtype=vol_dtype, sr_seed=sr_seed)
+                         vol_dtype=vol_dtype, sr_seed=sr_seed, n_max=cfg["batch"])
         st = {"excluded": 0.0, "t": [], "rmse": []}
 
         def cb(r, it):
@@ -164,6 +166,8 @@ def time_to_rmse(fbl, g, cfg, b32, xt, perms, proposer):
             st["t"].append(t_in - st["t0"] - st["excluded"])   # the iterate is complete (read back)
             e = float(torch.sqrt(torch.mean((r.x.float() - xt_dev) ** 2)))
             st["rmse"].append(e)
+            if len(st["rmse"]) % 50 == 0:   # progress of long runs (outside the timed intervals)
+                log("  %s: iteration %d, rmse %.4e" % (vol_dtype, len(st["rmse"]), e))
             st["excluded"] += time.perf_counter() - t_in
             if target is not None and e <= target:
                 raise Reached()
@@ -178,16 +182,20 @@ def time_to_rmse(fbl, g, cfg, b32, xt, perms, proposer):
             pass
         return run.history, st
 
-    hist_p, st_p = go(torch.from_numpy(b32).cuda(), "f32", None, None)
+    b_f32 = b32 if torch.is_tensor(b32) else torch.from_numpy(b32).cuda()
+    hist_p, st_p = go(b_f32, "f32", None, None)
     target = st_p["rmse"][-1]
     k_p = next(i for i, e in enumerate(st_p["rmse"]) if e <= target) + 1
-    b16 = torch.from_numpy(b32).cuda().half()
+    b16 = b_f32.half()
     hist_l, st_l = go(b16, "bf16", proposer, target, sr_seed=2024)
     k_l = len(hist_l)
     reached = st_l["rmse"][-1] <= target
-    hist_n, st_n = go(b16, "bf16", proposer, target)
-    hist_h, st_h = go(b16, "f16", proposer, target, sr_seed=2024)
-    hist_f, st_f = go(torch.from_numpy(b32).cuda(), "f32", proposer, target)
+    if "bf16_nearest" in variants:
+        hist_n, st_n = go(b16, "bf16", proposer, target)
+    if "f16" in variants:
+        hist_h, st_h = go(b16, "f16", proposer, target, sr_seed=2024)
+    if "f32" in variants:
+        hist_f, st_f = go(b_f32, "f32", proposer, target)
 
     def summary(hist, st, k):
         h = hist[:k]
@@ -195,17 +203,58 @@ def time_to_rmse(fbl, g, cfg, b32, xt, perms, proposer):
                 "fp_calls_per_iter": round(float(np.mean([2 + it.backtracks for it in h])), 3),
                 "backtracks_per_iter": round(float(np.mean([it.backtracks for it in h])), 3)}
 
-    return {
+    rec = {
         "rmse_target": target,
         "plain_f32": summary(hist_p, st_p, k_p),
         "learned_bf16": dict(summary(hist_l, st_l, k_l), reached=reached,
                              storage="BF16 volume (stochastic rounding), FP16 data"),
-        "learned_bf16_nearest": dict(summary(hist_n, st_n, len(hist_n)), reached=st_n["rmse"][-1] <= target),
-        "learned_f16": dict(summary(hist_h, st_h, len(hist_h)), reached=st_h["rmse"][-1] <= target,
-                            storage="FP16 volume (stochastic rounding), FP16 data"),
-        "learned_f32": dict(summary(hist_f, st_f, len(hist_f)), reached=st_f["rmse"][-1] <= target),
-        "speedup": round(st_p["t"][k_p - 1] / st_l["t"][k_l - 1], 3) if reached else None,
     }
+    if "bf16_nearest" in variants:
+        rec["learned_bf16_nearest"] = dict(summary(hist_n, st_n, len(hist_n)), reached=st_n["rmse"][-1] <= target)
+    if "f16" in variants:
+        rec["learned_f16"] = dict(summary(hist_h, st_h, len(hist_h)), reached=st_h["rmse"][-1] <= target,
+                                  storage="FP16 volume (stochastic rounding), FP16 data")
+    if "f32" in variants:
+        rec["learned_f32"] = dict(summary(hist_f, st_f, len(hist_f)), reached=st_f["rmse"][-1] <= target)
+    rec["speedup"] = round(st_p["t"][k_p - 1] / st_l["t"][k_l - 1], 3) if reached else None
+    return rec
+
+
+def combined_run(fbl, syn, name: str = "c5"):
+    """The full combined run on one GPU: plain FP32 FB-LISA against the learned initial step
+    with BF16 volume storage (stochastic rounding) and FP16 data, timed to the plain run's
+    final RMSE; the same with FP16 volume storage for comparison.  The data are exact line integrals of the workload's ellipsoid phantom plus
+    1% Gaussian noise, computed on the GPU (the host loop would take a quarter of an hour at
+    1024^3); the phantom is voxelised at one sample per voxel."""
+    import torch
+    cfg = syn.CONFIGS[name]
+    g = syn.config_geometry(name)
+    B = cfg["batch"]
+    seed = 1000 * int(name[1:])
+    t0 = time.perf_counter()
+    ells, xt = syn.phantom(g, cfg["k"], seed=seed, hi=cfg["hi"], sub=1)
+    t_ph = time.perf_counter() - t0
+    y = syn.ellipsoid_line_integrals_torch(g, ells, np.arange(g.n_views), device="cuda")
+    syn.add_noise_torch(y, 0.01, seed=seed + 1)
+    b32 = y.float()
+    del y
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    t_data = time.perf_counter() - t0
+    log("combined run %s: phantom %.1f s, data %.1f s" % (name, t_ph, t_data))
+    model, n_samples, curve = train_step_proposer(fbl, syn)
+    n_it = cfg["epochs"] * math.ceil(g.n_views / B)
+    perms = syn.view_permutations(g.n_views, n_it, seed=seed + 2)
+    # BF16 (the run's storage) and, for comparison, FP16 storage with the same proposer
+    tt = time_to_rmse(fbl, g, cfg, b32, xt, perms, fbl.LearnedStep(model), variants=("bf16", "f16"))
+    return {"mode": "combined run",
+            "workload": "%s: %d^3 ellipsoid phantom (%d ellipsoids, voxelised at 1 sample per voxel), %d views, "
+                        "%dx%d detector, mini-batch %d, %d epochs, prox [%g, %g], 1%% Gaussian noise on exact line "
+                        "integrals" % (name, g.nx, cfg["k"], g.n_views, g.nu, g.nv, B, cfg["epochs"], cfg["lo"],
+                                       cfg["hi"]),
+            "setup_s": round(t_data, 1),
+            "proposer": "5-64-64-1 perceptron trained on %d iterations of 200 seeded 64^3 runs" % n_samples,
+            "time_to_rmse": tt}
 
 
 def paper_shaped_run(fbl, syn, seconds: float, views: int = 72, n: int = 560, n0: int = 8, seed: int = 5600):
@@ -343,6 +392,9 @@ def main(argv=None):
     ap.add_argument("--paper-run", type=float, default=0.0, metavar="SECONDS",
                     help="instead of the benchmark: the paper's growing-batch variant with mu > 0 on a 560^3 / "
                          "72-view synthetic stand-in, for this many seconds")
+    ap.add_argument("--combined-run", default="", metavar="CONFIG",
+                    help="instead of the benchmark: the full combined run (plain FP32 against learned step + BF16 "
+                         "storage, time to the plain run's RMSE) at this workload, e.g. c5")
     ap.add_argument("--kernels", default="", metavar="CONFIGS",
                     help="instead of the benchmark: time the projector and step kernels alone at these workloads "
                          "(comma-separated, e.g. c3,c5)")
@@ -362,6 +414,9 @@ def main(argv=None):
     torch.cuda.set_device(0)
     if args.kernels:
         print(json.dumps(kernel_scaling(fbl, syn, [c for c in args.kernels.split(",") if c])), flush=True)
+        return 0
+    if args.combined_run:
+        print(json.dumps(combined_run(fbl, syn, args.combined_run)), flush=True)
         return 0
     if args.paper_run > 0:
         print(json.dumps(paper_shaped_run(fbl, syn, args.paper_run)), flush=True)

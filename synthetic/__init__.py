@@ -320,6 +320,61 @@ def ellipsoid_line_integrals(g: Geometry, ells: Sequence[Ellipsoid], views: Sequ
     return out
 
 
+
+def ellipsoid_line_integrals_torch(g: Geometry, ells: Sequence[Ellipsoid], views: Sequence[int], device="cuda",
+                                   out=None):
+    """ellipsoid_line_integrals with torch on `device`, for data sets too large for the host
+    loop (FP64, [B][nv][nu]; written into `out` when given, of any float dtype).
+
+    The same FP64 operations in the same order, per view and ellipsoid, over the whole
+    detector instead of the culled rectangle: a ray outside it misses the ellipsoid, its
+    discriminant is not positive and it adds exactly zero.
+    """
+    import torch
+    views = np.asarray(views, dtype=np.int64)
+    f64 = torch.float64
+    if out is None:
+        out = torch.empty((len(views), g.nv, g.nu), dtype=f64, device=device)
+    u = (torch.arange(g.nu, dtype=f64, device=device) - 0.5 * (g.nu - 1)) * g.du
+    v = (torch.arange(g.nv, dtype=f64, device=device) - 0.5 * (g.nv - 1)) * g.dv
+    dc = g.sod - g.sdd
+    for bi, vw in enumerate(views):
+        th = g.angles[vw]
+        c, s = math.cos(th), math.sin(th)
+        src = np.array([g.sod * c, g.sod * s, 0.0])
+        qx = dc * c + u * (-s)
+        qy = dc * s + u * c
+        dx = (qx - src[0])[None, :].expand(g.nv, g.nu)
+        dy = (qy - src[1])[None, :].expand(g.nv, g.nu)
+        dz = (v - src[2])[:, None].expand(g.nv, g.nu)
+        ray_len = torch.sqrt(dx * dx + dy * dy + dz * dz)
+        acc = torch.zeros((g.nv, g.nu), dtype=f64, device=device)
+        for e in ells:
+            M = (e.rot / e.axes[None, :]).T
+            o = M @ (src - e.center)
+            d0 = M[0, 0] * dx + M[0, 1] * dy + M[0, 2] * dz
+            d1 = M[1, 0] * dx + M[1, 1] * dy + M[1, 2] * dz
+            d2 = M[2, 0] * dx + M[2, 1] * dy + M[2, 2] * dz
+            A = d0 * d0 + d1 * d1 + d2 * d2
+            Bq = 2.0 * (o[0] * d0 + o[1] * d1 + o[2] * d2)
+            Cq = float(o @ o) - 1.0
+            disc = Bq * Bq - 4.0 * A * Cq
+            dt = torch.sqrt(torch.clamp(disc, min=0.0)) / A
+            acc += e.rho * (dt * ray_len)
+        out[bi] = acc
+    return out
+
+
+def add_noise_torch(y_clean, level: float, seed: int):
+    """add_noise in place on a torch tensor on its own device, with torch's seeded generator
+    (another random stream than add_noise's): y + sigma N(0, 1), sigma = level ||y|| / sqrt(n)."""
+    import torch
+    gen = torch.Generator(device=y_clean.device).manual_seed(seed)
+    sigma = level * float(torch.linalg.vector_norm(y_clean.double())) / math.sqrt(y_clean.numel())
+    for i in range(y_clean.shape[0]):   # one view at a time: no second full-size array
+        y_clean[i].add_(torch.empty_like(y_clean[i]).normal_(generator=gen).mul_(sigma))
+    return y_clean
+
 def _ray_distance_to_point(g: Geometry, views, point):
     src, pix = ray_endpoints(g, views)
     d = pix - src[:, None, None, :]
