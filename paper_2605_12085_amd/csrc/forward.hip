@@ -288,14 +288,37 @@ __global__ __launch_bounds__(256) void transpose_xy_kernel(const TV *__restrict_
         }
 }
 
-__global__ __launch_bounds__(256) void finalize_kernel(const double *__restrict__ partials, int64_t n, int ncomp,
-                                                       double scale, double *__restrict__ out)
+// out[c] = scale * sum_i partials[i * NC + c].  Thread t adds entries t, t + 256, ... in
+// that order, then the block sums the 256 thread sums in a fixed order.  Each thread
+// issues eight rounds of loads (all NC components of each) before adding them, so the
+// loads overlap instead of forming one dependent chain per component.
+template <int NC>
+__global__ __launch_bounds__(256) void finalize_kernel(const double *__restrict__ partials, int64_t n, double scale,
+                                                       double *__restrict__ out)
 {
+    constexpr int kU = 8;
     __shared__ double red[4];
-    for (int c = 0; c < ncomp; ++c) {
-        double s = 0.0;
-        for (int64_t i = threadIdx.x; i < n; i += 256) s += partials[i * ncomp + c];
-        const double tot = block_sum_256(s, red);
+    double s[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s[c] = 0.0;
+    int64_t i = threadIdx.x;
+    for (; i + (kU - 1) * 256 < n; i += kU * 256) {
+        double v[kU][NC];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) v[u][c] = partials[(i + u * 256) * NC + c];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) s[c] += v[u][c];
+    }
+    for (; i < n; i += 256)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) s[c] += partials[i * NC + c];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const double tot = block_sum_256(s[c], red);
         if (threadIdx.x == 0) out[c] = scale * tot;
     }
 }
@@ -395,7 +418,12 @@ hipError_t launch_forward(const fbl_plan *p, const void *x, const ViewList &vl, 
 
 hipError_t launch_finalize_sum(double *partials, int64_t n, int ncomp, double scale, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, st, (const double *)partials, n, ncomp, scale, out);
+    if (ncomp == 3)
+        hipLaunchKernelGGL(finalize_kernel<3>, dim3(1), dim3(256), 0, st, (const double *)partials, n, scale, out);
+    else if (ncomp == 1)
+        hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(256), 0, st, (const double *)partials, n, scale, out);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
