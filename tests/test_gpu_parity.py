@@ -276,6 +276,38 @@ def test_step_parity(fbl, orc):
             assert red[2] == pytest.approx(gg, rel=1e-12)
 
 
+
+def test_reductions_over_many_partials(fbl, orc):
+    # More than 2048 per-block partials, so the final one-block sum takes its batched
+    # path: the prox trial at 128^3 runs 2048 blocks, and a 512^2 detector gives
+    # 64 forward blocks per view (2560 for 40 views).
+    import torch
+    g = syn.config_geometry("c4")
+    assert g.d == 128 ** 3
+    rng = np.random.default_rng(41)
+    x = rng.uniform(0, 0.02, g.vol_shape).astype(np.float32)
+    grad = (rng.standard_normal(g.vol_shape) * 3.0).astype(np.float32)
+    with fbl.Plan(g) as plan:
+        red = torch.zeros(3, dtype=torch.float64, device="cuda")
+        xb, red = fbl.fb_lisa_step(plan, _t(x), _t(grad), 1e-3, 0.5, 0.0, 0.03, red=red)
+        xr, inner, sq, gg = orc.prox_step(x, grad, 1e-3, 0.5, 0.0, 0.03, storage=np.float32)
+        red = red.cpu().numpy()
+        assert red[0] == pytest.approx(inner, rel=1e-9)
+        assert red[1] == pytest.approx(sq, rel=1e-9)
+        assert red[2] == pytest.approx(gg, rel=1e-12)
+        xb = xb.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(xb - xr) <= np.spacing(np.abs(xr).astype(np.float32)).astype(np.float64))
+    # 0.5 mm voxels and pixels: rows 0.5 voxels apart at the centre (a wide detector,
+    # most of whose rays miss the volume, still runs 64 forward blocks per view)
+    g2 = syn.Geometry(64, 64, 64, 0.5, 0.5, 0.5, 512, 512, 0.5, 0.5, 500.0, 1000.0, 40)
+    x2 = rng.uniform(0, 0.02, g2.vol_shape).astype(np.float32)
+    views = np.arange(40, dtype=np.int32)
+    with fbl.Plan(g2, max_batch=40) as plan:
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        y = fbl.fb_lisa_forward(plan, _t(x2), views, loss=loss, loss_scale=0.5)
+        yy = y.cpu().numpy().astype(np.float64)
+        assert float(loss[0]) == pytest.approx(0.5 * np.sum(yy * yy), rel=1e-12)
+
 def test_chunked_batches_and_duplicates(fbl, orc):
     # more views than one launch carries (256), duplicates and B = 1
     g = syn.Geometry(12, 10, 8, 1.0, 1.0, 1.0, 16, 12, 1.5, 1.5, 300.0, 600.0, 300)
