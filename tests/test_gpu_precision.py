@@ -87,15 +87,21 @@ def _storage_ulp(v, st):
 
 
 @pytest.mark.parametrize("st", ["bf16", "f16"])
-def test_step_16bit_rounds_once_like_the_oracle(fbl, orc, st):
+@pytest.mark.parametrize("shape", ["odd", "128"])
+def test_step_16bit_rounds_once_like_the_oracle(fbl, orc, st, shape):
+    # "odd": 43,993 voxels (a tail of one after the four-voxel passes), three settings;
+    # "128": 128^3, where each thread makes several grid-stride passes of four voxels
     import torch
-    g = ODD
+    g = ODD if shape == "odd" else syn.config_geometry("c4")
+    settings = ((1e-3, 0.0, 0.0, math.inf), (2.5e-3, 0.7, 0.0, 0.03), (1e-4, 2.0, 0.001, 0.025))
+    if shape == "128":
+        settings = settings[1:2]
     rng = np.random.default_rng(22)
     xs = orc.round_storage(rng.uniform(0, 0.03, g.vol_shape), st)
     xs[rng.random(g.vol_shape) < 0.2] = 0.0
     grad = (rng.standard_normal(g.vol_shape) * 3.0).astype(np.float32)
     with fbl.Plan(g, vol_dtype=st) as plan:
-        for alpha, mu, lo, hi in ((1e-3, 0.0, 0.0, math.inf), (2.5e-3, 0.7, 0.0, 0.03), (1e-4, 2.0, 0.001, 0.025)):
+        for alpha, mu, lo, hi in settings:
             red = torch.zeros(3, dtype=torch.float64, device="cuda")
             xb, red = fbl.fb_lisa_step(plan, _dev(xs, st), torch.from_numpy(grad).cuda(), alpha, mu, lo, hi,
                                        red=red)
