@@ -327,11 +327,15 @@ def paper_shaped_run(fbl, syn, seconds: float, views: int = 72, n: int = 560, n0
     }
 
 
-def kernel_scaling(fbl, syn, names, reps=5):
+def kernel_scaling(fbl, syn, names, reps=5, storage="f32"):
     """Projector and step kernel times alone at several workload sizes, on a voxelised phantom
     and a seeded residual (no measured data needed): forward, backprojection and prox trial
-    of one mini-batch of the workload's size, mean over `reps` launches after a clock warm-up."""
+    of one mini-batch of the workload's size, mean over `reps` launches after a clock warm-up.
+    `storage` is the volume's storage type (f32, bf16 or f16); the view model then counts
+    its bytes per voxel, and the prox trial moves 4 + 2 x (bytes per voxel) bytes per voxel."""
     import torch
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[storage]
+    vb = 4 if storage == "f32" else 2
     out = []
     for name in names:
         cfg = syn.CONFIGS[name]
@@ -339,11 +343,11 @@ def kernel_scaling(fbl, syn, names, reps=5):
         B = cfg["batch"]
         t0 = time.perf_counter()
         _, xt = syn.phantom(g, cfg["k"], seed=1000 * int(name[1:]), hi=cfg["hi"], sub=1)
-        x = torch.from_numpy(xt.astype(np.float32)).cuda()
+        x = torch.from_numpy(xt.astype(np.float32)).cuda().to(tdt).contiguous()
         del xt
         views = syn.view_permutations(g.n_views, 1, seed=7)[0][:B]
         r = torch.from_numpy(syn.random_projections(g, B, seed=8, scale=0.1)).cuda()
-        with fbl.Plan(g, max_batch=B) as plan:
+        with fbl.Plan(g, storage, "f32", max_batch=B) as plan:
             plan_s = time.perf_counter() - t0
             y = fbl.fb_lisa_forward(plan, x, views)
             gr = fbl.fb_lisa_backproject(plan, r, views)
@@ -357,8 +361,9 @@ def kernel_scaling(fbl, syn, names, reps=5):
             torch.cuda.synchronize()
             kt = plan.timing_read()
         t = {k: ms / n * 1e-3 for k, (ms, n) in kt.items() if n}
-        byts = B * (g.d * 4 + 4 * g.n_p)
+        byts = B * (g.d * vb + 4 * g.n_p)
         rec = {"workload": "%s: %d^3, %d views, %dx%d detector, batch %d" % (name, g.nx, g.n_views, g.nu, g.nv, B),
+               "storage": storage,
                "setup_s": round(plan_s, 1),
                "forward_us": round(t["forward"] * 1e6, 1), "backproject_us": round(t["backproject"] * 1e6, 1),
                "step_us": round(t["step"] * 1e6, 1),
@@ -366,12 +371,12 @@ def kernel_scaling(fbl, syn, names, reps=5):
                "backproject_gups": round(g.d * B / t["backproject"] / 1e9, 1),
                "forward_hbm_frac": round(byts / t["forward"] / 8e12, 4),
                "backproject_hbm_frac": round(byts / t["backproject"] / 8e12, 4),
-               "step_hbm_frac": round(12 * g.d / t["step"] / 8e12, 4)}
+               "step_hbm_frac": round((4 + 2 * vb) * g.d / t["step"] / 8e12, 4)}
         log(json.dumps(rec))
         out.append(rec)
         del x, r, y, gr, xb
         torch.cuda.empty_cache()
-    return {"mode": "kernel scaling", "fp32": out}
+    return {"mode": "kernel scaling", storage: out}
 
 
 def main(argv=None):
@@ -392,6 +397,8 @@ def main(argv=None):
     ap.add_argument("--paper-run", type=float, default=0.0, metavar="SECONDS",
                     help="instead of the benchmark: the paper's growing-batch variant with mu > 0 on a 560^3 / "
                          "72-view synthetic stand-in, for this many seconds")
+    ap.add_argument("--kernel-storage", default="f32", choices=("f32", "bf16", "f16"),
+                    help="volume storage type for --kernels")
     ap.add_argument("--combined-run", default="", metavar="CONFIG",
                     help="instead of the benchmark: the full combined run (plain FP32 against learned step + BF16 "
                          "storage, time to the plain run's RMSE) at this workload, e.g. c5")
@@ -413,7 +420,8 @@ def main(argv=None):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.kernels:
-        print(json.dumps(kernel_scaling(fbl, syn, [c for c in args.kernels.split(",") if c])), flush=True)
+        print(json.dumps(kernel_scaling(fbl, syn, [c for c in args.kernels.split(",") if c],
+                                        storage=args.kernel_storage)), flush=True)
         return 0
     if args.combined_run:
         print(json.dumps(combined_run(fbl, syn, args.combined_run)), flush=True)
