@@ -35,7 +35,7 @@ __device__ __forceinline__ void store_vec(T *__restrict__ p, int64_t q, const T 
 // Voxels per thread and pass.  With 16-bit storage four voxels share one 8-byte access
 // of x and of x-bar (and one 16-byte access of g); that measured 5-20% faster than one
 // voxel per pass at 128^3 to 1024^3.  With FP32 storage one voxel per pass streamed
-// faster at 512^3 and 1024^3 (16-byte accesses lost 9-12% there) and equally at 256^3.
+// faster at 512^3 and 1024^3 (16-byte accesses lost 9-14% there) and equally at 256^3.
 template <typename TV> constexpr int step_vec() { return sizeof(TV) == 2 ? 4 : 1; }
 
 // SR: round the trial point stochastically (counter-based, keyed) instead of to nearest.
