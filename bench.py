@@ -42,10 +42,11 @@ KERNEL_SOURCES = {"fp_kernel": "forward.hip", "bp_kernel": "backproject.hip"}
 
 
 def kernel_source_hash(kernel: str) -> str:
-    """Hash of a kernel's source and its device helpers, comments and spacing removed, so
-    that a counter summary stays valid across edits that change no code."""
+    """Hash of a kernel's source, its device helpers, the shared declarations and the host
+    code that chooses its launch shapes (plan.hip), comments and spacing removed, so that a
+    counter summary stays valid across edits that change no code."""
     h = hashlib.sha256()
-    for f in (KERNEL_SOURCES[kernel], "device_util.h"):
+    for f in (KERNEL_SOURCES[kernel], "device_util.h", "common.h", "plan.hip"):
         with open(os.path.join(ROOT, "paper_2605_12085_amd", "csrc", f)) as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)

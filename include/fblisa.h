@@ -96,9 +96,13 @@ typedef struct fbl_plan fbl_plan;
 FBL_API int fbl_geometry_check(const fbl_geometry *g);
 
 /* Create a plan on the current HIP device: validates the geometry, computes the per-view,
- * per-column ray parameters in FP64 on the host, and allocates the plan's device tables,
- * its reduction workspace and a [max_batch][nv][nu] FP32 scratch used by the
- * backprojection.  max_batch in [1, n_views].  vol_dtype is FBL_F32, FBL_BF16 or
+ * per-column ray parameters in FP64 on the host, and allocates the plan's device memory:
+ * its tables (about 64 bytes per view and detector column), its FP64 reduction partials,
+ * a [max_batch][nv][nu] FP32 scratch for the backprojection's weighted residual, and a
+ * y-fastest copy [nz][nx][ny] of the volume in vol_dtype that the forward projection
+ * refreshes for views marching x = const slices.  Nothing is allocated after this call,
+ * so the three compute calls keep the argument lists of the method's operations.
+ * max_batch in [1, n_views].  vol_dtype is FBL_F32, FBL_BF16 or
  * FBL_F16 (x and xbar); proj_dtype is FBL_F32, FBL_BF16 or FBL_F16 (b).  Storage types
  * only change what is read and written: every ray sum and the residual are formed in
  * FP32 and every reduction in FP64.  On failure *out is NULL.
@@ -138,6 +142,32 @@ FBL_API int fb_lisa_backproject(fbl_plan *plan, const float *r, const int32_t *v
  *             order (deterministic). */
 FBL_API int fb_lisa_step(fbl_plan *plan, const void *x, const float *g, double alpha, double mu, double lo, double hi,
                  void *xbar, double *red_dev, void *stream);
+
+/* fb_lisa_step on an FP32 master iterate with a 16-bit copy for the projector (the
+ * precision form in which the volume the projector reads is stored in 16 bits while the
+ * iterate itself keeps FP32): the plan's vol_dtype must be FBL_BF16 or FBL_F16.
+ *   x, xbar   device FP32 [nz][ny][nx]: xbar = min(max(x - alpha g - alpha mu, lo), hi),
+ *             formed in FP64 and rounded once to FP32
+ *   xbar16    device, vol_dtype [nz][ny][nx]: xbar rounded to nearest (ties to even), the
+ *             input of the next fb_lisa_forward of the trial point
+ *   red_dev   as fb_lisa_step, on the FP32 values of x and xbar.
+ * None of x, g, xbar, xbar16 may alias another.  FBL_E_DTYPE for an FP32 plan. */
+FBL_API int fb_lisa_step_mixed(fbl_plan *plan, const float *x, const float *g, double alpha, double mu, double lo,
+                               double hi, float *xbar, void *xbar16, double *red_dev, void *stream);
+
+/* FP64 instantiation of the projector pair, for checks (finite differences, adjoint
+ * identity, comparison with an FP64 reference): the same operator A as fb_lisa_forward and
+ * fb_lisa_backproject with every position, weight and sum in FP64.  Plain kernels (one
+ * thread per ray, the transpose scattered with FP64 atomic additions), far slower than
+ * the FP32 path; not part of the method's loop.
+ *   fb_lisa_forward_f64:     x device FP64 [nz][ny][nx]; y device FP64 [B][nv][nu] = A_views x
+ *   fb_lisa_backproject_f64: r device FP64 [B][nv][nu]; g device FP64 [nz][ny][nx],
+ *                            overwritten with grad_scale * A_views^T r (eq. 2.5)
+ * views, B and errors as fb_lisa_forward. */
+FBL_API int fb_lisa_forward_f64(fbl_plan *plan, const double *x, const int32_t *views, int32_t B, double *y,
+                                void *stream);
+FBL_API int fb_lisa_backproject_f64(fbl_plan *plan, const double *r, const int32_t *views, int32_t B,
+                                    double grad_scale, double *g, void *stream);
 
 /* Learned initial step of the line search (Alg. 1 Step 2c starts from a proposed step;
  * the backtracking on (2.3) still accepts or rejects every proposal).  The proposer is a

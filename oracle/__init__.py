@@ -237,13 +237,6 @@ def objective_and_gradient(g, x, b_full, views, n_theta: Optional[int] = None):
     return f, grad, r
 
 
-def full_objective(g, x, b_full, mu: float = 0.0) -> float:
-    """F(x) = 1/2 ||A x - b||^2 + mu ||x||_1 of problem (2.1) (x assumed feasible)."""
-    allv = np.arange(g.n_views, dtype=np.int32)
-    r = forward(g, x, allv) - _f64(b_full)
-    return 0.5 * float(np.dot(r.ravel(), r.ravel())) + mu * float(np.abs(_f64(x)).sum())
-
-
 def prox(v, alpha: float, mu: float, lo: float = 0.0, hi: float = math.inf) -> np.ndarray:
     """prox of alpha * (mu ||.||_1 + indicator[lo, hi]) for 0 <= lo <= hi.
 
@@ -466,7 +459,8 @@ def fblisa(g, b_full, *, epochs: int, n0: int, alpha0: float = 1e-3, beta: float
            x0: Optional[np.ndarray] = None, perms: Optional[np.ndarray] = None,
            j_max: int = 50, decisions: Optional[Sequence[Sequence[bool]]] = None,
            alpha_init: Optional[Callable[[int], float]] = None,
-           max_iters: Optional[int] = None, callback=None, storage=None, sr_seed: Optional[int] = None):
+           max_iters: Optional[int] = None, callback=None, storage=None, sr_seed: Optional[int] = None,
+           copy_storage=None):
     """Algorithm 1 (FB-LISA) in FP64 with n = n_theta (one f_i per projection angle).
 
     perms[k] is a permutation of the views for iteration k; the mini-batch is its
@@ -474,8 +468,17 @@ def fblisa(g, b_full, *, epochs: int, n0: int, alpha0: float = 1e-3, beta: float
     each trial.  ``alpha_init(k)`` replaces alpha_0 as the first trial step.
     ``storage`` keeps the iterates rounded to a storage type (the arithmetic stays FP64),
     to nearest or, with ``sr_seed``, stochastically with trial_key(sr_seed, k, j).
+    ``copy_storage`` ("bf16" or "f16") is the mixed form: the iterates are kept in FP32 and
+    the objective and its gradient are evaluated at their copies rounded to nearest in
+    copy_storage (what a projector reading 16-bit values sees); the prox step and the inner
+    products of (2.3) use the FP32 iterates.
     Returns (x, records).
     """
+    if copy_storage is not None:
+        if sr_seed is not None:
+            raise ValueError("the mixed form keeps FP32 iterates: no stochastic rounding")
+        storage = "f32"
+    seen = (lambda z: z) if copy_storage is None else (lambda z: round_storage(z, copy_storage))
     n = g.n_views
     n_max = n if n_max is None else n_max
     if C is None:
@@ -490,14 +493,14 @@ def fblisa(g, b_full, *, epochs: int, n0: int, alpha0: float = 1e-3, beta: float
             if max_iters is not None and k >= max_iters:
                 return x, records
             views = perms[k][:nt] if perms is not None else np.arange(nt)
-            f0, grad, _ = objective_and_gradient(g, x, b_full, views)
+            f0, grad, _ = objective_and_gradient(g, seen(x), b_full, views)
             a0 = alpha0 if alpha_init is None else alpha_init(k)
             dec = None
             if decisions is not None:
                 dk = decisions[k]
                 dec = lambda j, dk=dk: dk[j]
             alpha, xbar, f_bar, trials = line_search(
-                lambda z: objective(g, z, b_full, views), x, f0, grad, a0, beta, mu, lo, hi, j_max, dec,
+                lambda z: objective(g, seen(z), b_full, views), x, f0, grad, a0, beta, mu, lo, hi, j_max, dec,
                 storage, None if sr_seed is None else (lambda j, k=k: trial_key(sr_seed, k, j)))
             records.append(IterRecord(t, k, np.asarray(views).copy(), f0, alpha, len(trials) - 1, trials))
             x = xbar
@@ -528,15 +531,21 @@ def power_iteration_L(g, views, n_theta: Optional[int] = None, iters: int = 200,
 # ----------------------------------------------------------------------------------
 
 def rmse(x, x_true) -> float:
+    """Root-mean-square error over every voxel (the time-to-quality target of the
+    benchmark; Section 3 reports errors of the reconstruction against the reference)."""
     d = _f64(x) - _f64(x_true)
     return math.sqrt(float(np.dot(d.ravel(), d.ravel())) / d.size)
 
 
 def relative_error(x, x_true) -> float:
+    """RE = ||x - x_true||_2 / ||x_true||_2 (Section 3 leaves RE undefined; this is the
+    usual reading)."""
     d = _f64(x) - _f64(x_true)
     return float(np.linalg.norm(d.ravel()) / np.linalg.norm(_f64(x_true).ravel()))
 
 
 def psnr(x, x_true) -> float:
+    """PSNR in dB with the peak taken as the largest value of x_true (Section 3 leaves the
+    peak unstated): 20 log10(max x_true / RMSE)."""
     peak = float(_f64(x_true).max())
     return 20.0 * math.log10(peak / rmse(x, x_true))

@@ -26,7 +26,7 @@ _PROJ_DTYPES = {"f32": (FBL_F32, torch.float32), "bf16": (FBL_BF16, torch.bfloat
 EXPORTED = ("fbl_geometry_check", "fbl_plan_create", "fbl_plan_destroy", "fb_lisa_forward",
             "fb_lisa_backproject", "fb_lisa_step", "fb_lisa_step_sr", "fbl_mlp_workspace_bytes", "fbl_mlp_forward",
             "fbl_mlp_loss_grad", "fbl_mlp_adam", "fbl_timing_enable", "fbl_timing_select", "fbl_timing_read",
-            "fbl_last_error")
+            "fbl_last_error", "fb_lisa_step_mixed", "fb_lisa_forward_f64", "fb_lisa_backproject_f64")
 MLP_IN, MLP_HIDDEN = 5, 64
 MLP_NPARAMS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 KERNELS = ("forward", "transpose", "finalize", "prescale", "backproject", "step")  # FBL_K_* order
@@ -63,6 +63,10 @@ def _load() -> ctypes.CDLL:
                                  P, P, P]
     lib.fb_lisa_step_sr.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_uint64, P, P, P]
+    lib.fb_lisa_step_mixed.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       P, P, P, P]
+    lib.fb_lisa_forward_f64.argtypes = [P, P, P, ctypes.c_int32, P, P]
+    lib.fb_lisa_backproject_f64.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_double, P, P]
     lib.fbl_mlp_workspace_bytes.argtypes = [ctypes.c_int64]
     lib.fbl_mlp_workspace_bytes.restype = ctypes.c_size_t
     lib.fbl_mlp_forward.argtypes = [P, P, ctypes.c_int64, P, P]
@@ -75,8 +79,9 @@ def _load() -> ctypes.CDLL:
     lib.fbl_last_error.argtypes = []
     lib.fbl_last_error.restype = ctypes.c_char_p
     for name in ("fbl_geometry_check", "fbl_plan_create", "fb_lisa_forward", "fb_lisa_backproject",
-                 "fb_lisa_step", "fb_lisa_step_sr", "fbl_mlp_forward", "fbl_mlp_loss_grad", "fbl_mlp_adam", "fbl_timing_enable",
-                 "fbl_timing_select", "fbl_timing_read"):
+                 "fb_lisa_step", "fb_lisa_step_sr", "fb_lisa_step_mixed", "fb_lisa_forward_f64",
+                 "fb_lisa_backproject_f64", "fbl_mlp_forward", "fbl_mlp_loss_grad", "fbl_mlp_adam",
+                 "fbl_timing_enable", "fbl_timing_select", "fbl_timing_read"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -249,6 +254,57 @@ def fb_lisa_step(plan: Plan, x: torch.Tensor, g: torch.Tensor, alpha: float, mu:
                                    float(hi), int(key) & 0xFFFFFFFFFFFFFFFF, xbar.data_ptr(), red.data_ptr(),
                                    _stream(stream)))
     return xbar, red
+
+
+def fb_lisa_step_mixed(plan: Plan, x: torch.Tensor, g: torch.Tensor, alpha: float, mu: float = 0.0,
+                       lo: float = 0.0, hi: float = math.inf, xbar: Optional[torch.Tensor] = None,
+                       xbar16: Optional[torch.Tensor] = None, red: Optional[torch.Tensor] = None, stream=None):
+    """Prox trial on an FP32 master iterate: xbar (FP32) = prox(x - alpha g) and its 16-bit copy
+    xbar16 (the plan's volume storage type, the projector's input); red as fb_lisa_step, on
+    the FP32 values."""
+    _need(x, "x", torch.float32, plan.vol_shape)
+    _need(g, "g", torch.float32, plan.vol_shape)
+    if xbar is None:
+        xbar = torch.empty_like(x)
+    _need(xbar, "xbar", torch.float32, plan.vol_shape)
+    if xbar16 is None:
+        xbar16 = torch.empty(plan.vol_shape, dtype=plan.vol_torch, device=x.device)
+    _need(xbar16, "xbar16", plan.vol_torch, plan.vol_shape)
+    if red is None:
+        red = torch.empty(3, dtype=torch.float64, device=x.device)
+    _need(red, "red", torch.float64)
+    if red.numel() < 3:
+        raise ValueError("red needs three elements")
+    _check(lib.fb_lisa_step_mixed(plan.handle, x.data_ptr(), g.data_ptr(), float(alpha), float(mu), float(lo),
+                                  float(hi), xbar.data_ptr(), xbar16.data_ptr(), red.data_ptr(), _stream(stream)))
+    return xbar, xbar16, red
+
+
+def fb_lisa_forward_f64(plan: Plan, x: torch.Tensor, views: Sequence[int], y: Optional[torch.Tensor] = None,
+                        stream=None) -> torch.Tensor:
+    """y = A_views x with the FP64 check kernels (x FP64 [nz][ny][nx], y FP64 [B][nv][nu])."""
+    v = _views(views)
+    _need(x, "x", torch.float64, plan.vol_shape)
+    if y is None:
+        y = torch.empty((len(v), plan.nv, plan.nu), dtype=torch.float64, device=x.device)
+    _need(y, "y", torch.float64, (len(v), plan.nv, plan.nu))
+    _check(lib.fb_lisa_forward_f64(plan.handle, x.data_ptr(), v.ctypes.data, len(v), y.data_ptr(), _stream(stream)))
+    return y
+
+
+def fb_lisa_backproject_f64(plan: Plan, r: torch.Tensor, views: Sequence[int], grad_scale: Optional[float] = None,
+                            g: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """g = grad_scale * A_views^T r with the FP64 check kernels (default scale n_theta/B)."""
+    v = _views(views)
+    _need(r, "r", torch.float64, (len(v), plan.nv, plan.nu))
+    if g is None:
+        g = torch.empty(plan.vol_shape, dtype=torch.float64, device=r.device)
+    _need(g, "g", torch.float64, plan.vol_shape)
+    if grad_scale is None:
+        grad_scale = plan.n_views / float(len(v))
+    _check(lib.fb_lisa_backproject_f64(plan.handle, r.data_ptr(), v.ctypes.data, len(v), float(grad_scale),
+                                       g.data_ptr(), _stream(stream)))
+    return g
 
 
 # -- learned initial step: perceptron kernels --------------------------------------------

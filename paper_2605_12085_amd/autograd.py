@@ -12,8 +12,9 @@ A_N.  Both directions run in the library's kernels:
 
 Because each backward is itself one of these differentiable operations, higher-order
 derivatives (for instance Hessian-vector products A_N^T A_N v) are available too.
-Volumes are FP32 [nz][ny][nx] CUDA tensors in the plan's layout; projections FP32
-[B][nv][nu].
+Volumes are [nz][ny][nx] CUDA tensors in the plan's layout, projections [B][nv][nu]:
+FP32 tensors run the library's fast kernels, FP64 tensors its FP64 check instantiation
+(project and backproject), so that torch.autograd.gradcheck can work in true FP64.
 """
 from __future__ import annotations
 
@@ -23,7 +24,20 @@ import numpy as np
 import torch
 from torch.autograd.function import once_differentiable
 
-from ._lib import Plan, fb_lisa_backproject, fb_lisa_forward
+from ._lib import Plan, fb_lisa_backproject, fb_lisa_backproject_f64, fb_lisa_forward, fb_lisa_forward_f64
+
+
+def _fp(plan, x, views):
+    # FP64 tensors take the FP64 check instantiation of the pair, FP32 ones the fast path
+    if x.dtype == torch.float64:
+        return fb_lisa_forward_f64(plan, x.contiguous(), views)
+    return fb_lisa_forward(plan, x.contiguous(), views)
+
+
+def _bp(plan, r, views):
+    if r.dtype == torch.float64:
+        return fb_lisa_backproject_f64(plan, r.contiguous(), views, grad_scale=1.0)
+    return fb_lisa_backproject(plan, r.contiguous(), views, grad_scale=1.0)
 
 
 def _as_views(views) -> np.ndarray:
@@ -34,7 +48,7 @@ class _Project(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x: torch.Tensor, plan: Plan, views: np.ndarray) -> torch.Tensor:
         ctx.plan, ctx.views = plan, views
-        return fb_lisa_forward(plan, x.contiguous(), views)
+        return _fp(plan, x, views)
 
     @staticmethod
     def backward(ctx, grad_y: torch.Tensor):
@@ -45,7 +59,7 @@ class _Backproject(torch.autograd.Function):
     @staticmethod
     def forward(ctx, r: torch.Tensor, plan: Plan, views: np.ndarray) -> torch.Tensor:
         ctx.plan, ctx.views = plan, views
-        return fb_lisa_backproject(plan, r.contiguous(), views, grad_scale=1.0)
+        return _bp(plan, r, views)
 
     @staticmethod
     def backward(ctx, grad_g: torch.Tensor):

@@ -40,6 +40,11 @@ struct ColParam {
     int32_t pad;
 };
 
+// FP64 path-length factors of a column for the FP64 check kernels: w = wa * sqrt(l2 + v^2).
+struct ColParam64 {
+    double wa, l2;
+};
+
 // Per-view quantities used by the voxel-driven backprojection to find the detector
 // columns near a voxel: the projection u(p) = sdd (p.e_u)/(sod - p.n) of a point p.
 struct ViewParam {
@@ -76,6 +81,7 @@ struct fbl_plan {
     int32_t vol_dtype, proj_dtype, max_batch;
     fbl::Geo geo;
     fbl::ColParam *d_col;
+    fbl::ColParam64 *d_col64;     // FP64 path-length factors (FP64 check kernels only)
     double *d_rowV;
     float *d_rowV2;
     fbl::ViewParam *d_view;
@@ -102,6 +108,11 @@ struct fbl_plan {
 
 namespace fbl {
 
+// Thread-local error message read by fbl_last_error: set_error stores a printf-style
+// message and returns `code`; clear_error empties it and returns FBL_OK.
+int set_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int clear_error();
+
 // Launch functions (stream-ordered, no synchronisation).  Each returns hipSuccess or the
 // launch error.
 hipError_t launch_transpose(const fbl_plan *p, const void *x, hipStream_t st);
@@ -121,12 +132,22 @@ hipError_t launch_step(const fbl_plan *p, const void *x, const float *g, double 
                        double hi, bool stochastic, uint64_t key, void *xbar, int64_t *n_partials_used,
                        hipStream_t st);
 
+// FP64 check instantiation of the projector pair (y and r point at the chunk's rows).
+hipError_t launch_forward64(const fbl_plan *p, const double *x, const ViewList &vl, int nb, double *y,
+                            hipStream_t st);
+hipError_t launch_backproject64(const fbl_plan *p, const double *r, const ViewList &vl, int nb, double scale,
+                                bool accumulate, double *g, hipStream_t st);
+
 size_t mlp_workspace_bytes(int64_t n);
 hipError_t launch_mlp_forward(const float *prm, const float *X, int64_t n, float *out, hipStream_t st);
 hipError_t launch_mlp_loss_grad(const float *prm, const float *X, const float *t, int64_t n, float *grad,
                                 double *loss, void *work, hipStream_t st);
 hipError_t launch_mlp_adam(float *prm, const float *grad, float *m, float *v, int64_t step, double lr, double b1,
                            double b2, double eps, hipStream_t st);
+
+// Prox trial on an FP32 master iterate that also writes the 16-bit copy (plan's vol_dtype).
+hipError_t launch_step_mixed(const fbl_plan *p, const float *x, const float *g, double alpha, double mu, double lo,
+                             double hi, float *xbar, void *xbar16, int64_t *n_partials_used, hipStream_t st);
 
 int step_blocks(const fbl_plan *p);
 int backproject_tile();   // in-slice tile extent of the backprojection (voxels)

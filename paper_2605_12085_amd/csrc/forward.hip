@@ -16,6 +16,11 @@
 //   - When a launch has too few rays to fill the chip, the waves of a block split the
 //     slice march of the same rays (PARTS parts of whole chunks) and add their sums in a
 //     fixed order at the end.
+//   - Launch order: the block index runs over detector column tiles fastest, then views,
+//     then row tiles.  A row tile's rays cross one horizontal band of the volume, so the
+//     blocks resident at one time (every view's column tiles of a few row tiles) read the
+//     same band, which the last-level cache then serves to all views of the batch instead
+//     of each view reading the volume from HBM.
 #include "common.h"
 #include "device_util.h"
 
@@ -66,17 +71,22 @@ __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
 {
     __shared__ float line[KB * kThreads];
     __shared__ double red[4];
-    const int bi = blockIdx.y;
-    const int view = vl.v[bi];
     const int tiles_u = (geo.nu + kCols - 1) / kCols;
+    // linear block index -> (row tile, view, column tile), column tiles fastest
+    const int nbv = (int)gridDim.x / blocks_per_view;          // views in this launch
+    const int rt = (int)blockIdx.x / (nbv * tiles_u);
+    const int rem = (int)blockIdx.x - rt * nbv * tiles_u;
+    const int bi = rem / tiles_u;
+    const int tile = rt * tiles_u + (rem - bi * tiles_u);    // tile within the view (column fastest)
+    const int view = vl.v[bi];
     const int tid = threadIdx.x;
     const int lane = tid & (kCols - 1), wave = tid / kCols;
     constexpr int kGroups = kWaves / PARTS;
     static_assert(kGroups * PARTS == kWaves, "PARTS divides the waves of a block");
     static_assert((PARTS - 1) * kGroups * kRows * kCols <= KB * kThreads, "the line buffer holds the parts' sums");
     const int grp = wave % kGroups, part = wave / kGroups;
-    const int c = (blockIdx.x % tiles_u) * kCols + lane;
-    const int r0 = ((blockIdx.x / tiles_u) * kGroups + grp) * kRows;
+    const int c = (tile % tiles_u) * kCols + lane;
+    const int r0 = ((tile / tiles_u) * kGroups + grp) * kRows;
     const int nrows = max(0, min(kRows, geo.nv - r0));
     const bool active = c < geo.nu && nrows > 0;
 
@@ -248,7 +258,7 @@ __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
     }
     if (want_loss) {
         const double s = block_sum_256(sq, red);
-        if (tid == 0) partials[(int64_t)(first + bi) * blocks_per_view + blockIdx.x] = s;
+        if (tid == 0) partials[(int64_t)(first + bi) * blocks_per_view + tile] = s;
     }
 }
 
@@ -346,7 +356,7 @@ static hipError_t launch_fp_s(const fbl_plan *p, const void *x, const void *xt, 
 {
     DeviceTables tab{p->d_col, p->d_rowV, p->d_rowV2, p->d_view};
     const int bpv = forward_blocks_per_view(p->geo, S);
-    dim3 grid(bpv, nb);
+    dim3 grid(bpv * nb);
     hipLaunchKernelGGL((fp_kernel<TV, TB, KB, S>), grid, dim3(kThreads), 0, st, (const TV *)x, (const TV *)xt,
                        p->geo, tab, vl, first, (const TB *)b, y, p->d_partials, bpv, want_loss ? 1 : 0);
     return hipGetLastError();

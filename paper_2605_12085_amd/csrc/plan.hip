@@ -13,11 +13,12 @@
 using namespace fbl;
 
 namespace {
-
 thread_local std::string g_err;
+}
 
-int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
-int fail(int code, const char *fmt, ...)
+namespace fbl {
+
+int set_error(int code, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -28,15 +29,21 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
-int ok()
+int clear_error()
 {
     g_err.clear();
     return FBL_OK;
 }
 
+}  // namespace fbl
+
+namespace {
+
+int ok() { return clear_error(); }
+
 int hip_fail(hipError_t e, const char *what)
 {
-    return fail(FBL_E_HIP, "%s: %s", what, hipGetErrorString(e));
+    return set_error(FBL_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
@@ -94,43 +101,43 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 int check_geometry(const fbl_geometry *g)
 {
-    if (!g) return fail(FBL_E_INVALID, "geometry is NULL");
+    if (!g) return set_error(FBL_E_INVALID, "geometry is NULL");
     if (g->nx < 1 || g->ny < 1 || g->nz < 1 || g->nu < 1 || g->nv < 1 || g->n_views < 1)
-        return fail(FBL_E_GEOMETRY, "every count must be >= 1 (nx=%lld ny=%lld nz=%lld nu=%lld nv=%lld n_views=%lld)",
+        return set_error(FBL_E_GEOMETRY, "every count must be >= 1 (nx=%lld ny=%lld nz=%lld nu=%lld nv=%lld n_views=%lld)",
                     (long long)g->nx, (long long)g->ny, (long long)g->nz, (long long)g->nu, (long long)g->nv,
                     (long long)g->n_views);
     if (g->nx < 2 || g->ny < 2)
-        return fail(FBL_E_GEOMETRY, "nx and ny must be >= 2 (the in-slice interpolation needs two taps)");
+        return set_error(FBL_E_GEOMETRY, "nx and ny must be >= 2 (the in-slice interpolation needs two taps)");
     if (g->nx > (1 << 24) || g->ny > (1 << 24) || g->nz > (1 << 24) || g->nu > (1 << 24) || g->nv > (1 << 24))
-        return fail(FBL_E_GEOMETRY, "a dimension exceeds 2^24");
+        return set_error(FBL_E_GEOMETRY, "a dimension exceeds 2^24");
     if ((double)g->nx * (double)g->ny * (double)g->nz >= 2147483648.0)
-        return fail(FBL_E_GEOMETRY, "nx*ny*nz must be below 2^31");
-    if ((double)g->nu * (double)g->nv >= 2147483648.0) return fail(FBL_E_GEOMETRY, "nu*nv must be below 2^31");
-    if (g->n_views > (1 << 24)) return fail(FBL_E_GEOMETRY, "n_views exceeds 2^24");
+        return set_error(FBL_E_GEOMETRY, "nx*ny*nz must be below 2^31");
+    if ((double)g->nu * (double)g->nv >= 2147483648.0) return set_error(FBL_E_GEOMETRY, "nu*nv must be below 2^31");
+    if (g->n_views > (1 << 24)) return set_error(FBL_E_GEOMETRY, "n_views exceeds 2^24");
     if (!finite_pos(g->hx) || !finite_pos(g->hy) || !finite_pos(g->hz) || !finite_pos(g->du) || !finite_pos(g->dv))
-        return fail(FBL_E_GEOMETRY, "voxel and pixel sizes must be finite and positive");
-    if (!finite_pos(g->sod) || !std::isfinite(g->sdd)) return fail(FBL_E_GEOMETRY, "SOD must be finite and positive");
-    if (!(g->sdd > g->sod)) return fail(FBL_E_GEOMETRY, "SDD (%g) must exceed SOD (%g)", g->sdd, g->sod);
+        return set_error(FBL_E_GEOMETRY, "voxel and pixel sizes must be finite and positive");
+    if (!finite_pos(g->sod) || !std::isfinite(g->sdd)) return set_error(FBL_E_GEOMETRY, "SOD must be finite and positive");
+    if (!(g->sdd > g->sod)) return set_error(FBL_E_GEOMETRY, "SDD (%g) must exceed SOD (%g)", g->sdd, g->sod);
     // half-diagonal of the volume grown by two voxels on every side (the backprojection
     // projects points up to that far out)
     const double ex = 0.5 * (double)(g->nx + 4) * g->hx, ey = 0.5 * (double)(g->ny + 4) * g->hy,
                  ez = 0.5 * (double)(g->nz + 4) * g->hz;
     const double half = std::sqrt(ex * ex + ey * ey + ez * ez);
     if (!(g->sod > half) || !(g->sdd - g->sod > half))
-        return fail(FBL_E_GEOMETRY,
+        return set_error(FBL_E_GEOMETRY,
                     "the volume must lie strictly between source and detector: SOD=%g and SDD-SOD=%g must exceed "
                     "the padded half-diagonal %g",
                     g->sod, g->sdd - g->sod, half);
     if (g->angles)
         for (int64_t v = 0; v < g->n_views; ++v)
-            if (!std::isfinite(g->angles[v])) return fail(FBL_E_GEOMETRY, "angle %lld is not finite", (long long)v);
+            if (!std::isfinite(g->angles[v])) return set_error(FBL_E_GEOMETRY, "angle %lld is not finite", (long long)v);
     const double dz = max_abs_dz(*g);
     for (int64_t v = 0; v < g->n_views; ++v)
         for (int64_t iu = 0; iu < g->nu; ++iu) {
             const ColumnGeom cg = column_geom(*g, v, iu);
             const double mxy = std::fmax(std::fabs(cg.D[0]), std::fabs(cg.D[1]));
             if (!(mxy >= dz))
-                return fail(FBL_E_GEOMETRY,
+                return set_error(FBL_E_GEOMETRY,
                             "view %lld column %lld has rays whose dominant axis is z (cone angle too large)",
                             (long long)v, (long long)iu);
         }
@@ -142,7 +149,7 @@ int dev_upload(T **dst, const std::vector<T> &src)
 {
     *dst = nullptr;
     hipError_t e = hipMalloc((void **)dst, src.size() * sizeof(T));
-    if (e != hipSuccess) return fail(FBL_E_NOMEM, "hipMalloc of %zu bytes: %s", src.size() * sizeof(T), hipGetErrorString(e));
+    if (e != hipSuccess) return set_error(FBL_E_NOMEM, "hipMalloc of %zu bytes: %s", src.size() * sizeof(T), hipGetErrorString(e));
     e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy of plan table");
     return FBL_OK;
@@ -155,6 +162,7 @@ void free_plan(fbl_plan *p)
     (void)hipGetDevice(&cur);
     if (p->device >= 0 && cur != p->device) (void)hipSetDevice(p->device);
     (void)hipFree(p->d_col);
+    (void)hipFree(p->d_col64);
     (void)hipFree(p->d_rowV);
     (void)hipFree(p->d_rowV2);
     (void)hipFree(p->d_view);
@@ -175,19 +183,19 @@ void free_plan(fbl_plan *p)
 
 int check_call(const fbl_plan *p, const int32_t *views, int32_t B)
 {
-    if (!p) return fail(FBL_E_INVALID, "plan is NULL");
-    if (!views) return fail(FBL_E_INVALID, "views is NULL");
+    if (!p) return set_error(FBL_E_INVALID, "plan is NULL");
+    if (!views) return set_error(FBL_E_INVALID, "views is NULL");
     if (B < 1 || B > p->max_batch)
-        return fail(FBL_E_RANGE, "batch size %d outside [1, %d]", (int)B, (int)p->max_batch);
+        return set_error(FBL_E_RANGE, "batch size %d outside [1, %d]", (int)B, (int)p->max_batch);
     for (int32_t k = 0; k < B; ++k)
         if (views[k] < 0 || views[k] >= p->geom.n_views)
-            return fail(FBL_E_RANGE, "views[%d] = %d outside [0, %lld)", (int)k, (int)views[k],
+            return set_error(FBL_E_RANGE, "views[%d] = %d outside [0, %lld)", (int)k, (int)views[k],
                         (long long)p->geom.n_views);
     int cur = -1;
     hipError_t e = hipGetDevice(&cur);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if (cur != p->device)
-        return fail(FBL_E_INVALID, "the current device (%d) is not the plan's device (%d)", cur, p->device);
+        return set_error(FBL_E_INVALID, "the current device (%d) is not the plan's device (%d)", cur, p->device);
     return FBL_OK;
 }
 
@@ -227,23 +235,33 @@ ViewList chunk(const int32_t *views, int first, int nb)
     return vl;
 }
 
-int step_call(fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo, double hi,
-              bool stochastic, uint64_t key, void *xbar, double *red_dev, void *stream)
+// Argument checks shared by the prox-trial entry points (the plan is non-NULL).
+int check_step_args(const fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo, double hi,
+                    const void *xbar, const double *red_dev)
 {
-    if (!p) return fail(FBL_E_INVALID, "plan is NULL");
-    if (!x || !g || !xbar || !red_dev) return fail(FBL_E_INVALID, "x, g, xbar and red_dev must be non-NULL");
+    if (!x || !g || !xbar || !red_dev) return set_error(FBL_E_INVALID, "x, g, xbar and red_dev must be non-NULL");
     if (!aligned16(x) || !aligned16(g) || !aligned16(xbar) || !aligned8(red_dev))
-        return fail(FBL_E_INVALID, "arrays must be 16-byte aligned and red_dev 8-byte aligned");
-    if (xbar == x || (const void *)xbar == (const void *)g) return fail(FBL_E_INVALID, "xbar may not alias x or g");
-    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(FBL_E_INVALID, "alpha must be finite and > 0");
-    if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(FBL_E_INVALID, "mu must be finite and >= 0");
+        return set_error(FBL_E_INVALID, "arrays must be 16-byte aligned and red_dev 8-byte aligned");
+    if (xbar == x || (const void *)xbar == (const void *)g) return set_error(FBL_E_INVALID, "xbar may not alias x or g");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return set_error(FBL_E_INVALID, "alpha must be finite and > 0");
+    if (!(mu >= 0.0) || !std::isfinite(mu)) return set_error(FBL_E_INVALID, "mu must be finite and >= 0");
     if (!(lo >= 0.0) || !std::isfinite(lo) || !(hi >= lo))
-        return fail(FBL_E_INVALID, "bounds must satisfy 0 <= lo <= hi (lo finite)");
+        return set_error(FBL_E_INVALID, "bounds must satisfy 0 <= lo <= hi (lo finite)");
     int cur = -1;
     hipError_t e = hipGetDevice(&cur);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    if (cur != p->device) return fail(FBL_E_INVALID, "the current device is not the plan's device");
+    if (cur != p->device) return set_error(FBL_E_INVALID, "the current device is not the plan's device");
+    return FBL_OK;
+}
+
+int step_call(fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo, double hi,
+              bool stochastic, uint64_t key, void *xbar, double *red_dev, void *stream)
+{
+    if (!p) return set_error(FBL_E_INVALID, "plan is NULL");
+    int rc = check_step_args(p, x, g, alpha, mu, lo, hi, xbar, red_dev);
+    if (rc != FBL_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
     int64_t nparts = 0;
     e = timed(p, FBL_K_STEP, st,
               [&] { return launch_step(p, x, g, alpha, mu, lo, hi, stochastic, key, xbar, &nparts, st); });
@@ -268,20 +286,21 @@ int fbl_geometry_check(const fbl_geometry *g)
 
 int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype, int32_t max_batch, fbl_plan **out)
 {
-    if (!out) return fail(FBL_E_INVALID, "out is NULL");
+    if (!out) return set_error(FBL_E_INVALID, "out is NULL");
     *out = nullptr;
     int rc = check_geometry(g);
     if (rc != FBL_OK) return rc;
     if (vol_dtype != FBL_F32 && vol_dtype != FBL_BF16 && vol_dtype != FBL_F16)
-        return fail(FBL_E_DTYPE, "vol_dtype %d is not FBL_F32, FBL_BF16 or FBL_F16", (int)vol_dtype);
+        return set_error(FBL_E_DTYPE, "vol_dtype %d is not FBL_F32, FBL_BF16 or FBL_F16", (int)vol_dtype);
     if (proj_dtype != FBL_F32 && proj_dtype != FBL_BF16 && proj_dtype != FBL_F16)
-        return fail(FBL_E_DTYPE, "proj_dtype %d is not FBL_F32, FBL_BF16 or FBL_F16", (int)proj_dtype);
+        return set_error(FBL_E_DTYPE, "proj_dtype %d is not FBL_F32, FBL_BF16 or FBL_F16", (int)proj_dtype);
     if (max_batch < 1 || max_batch > g->n_views)
-        return fail(FBL_E_RANGE, "max_batch %d outside [1, n_views=%lld]", (int)max_batch, (long long)g->n_views);
+        return set_error(FBL_E_RANGE, "max_batch %d outside [1, n_views=%lld]", (int)max_batch, (long long)g->n_views);
 
+    // value-initialisation zeroes every plain field (the struct has no user-provided
+    // constructor) and constructs the vectors; defaults that are not zero follow
     fbl_plan *p = new fbl_plan();
-    p->timing_mask = (1u << FBL_K_COUNT) - 1u;
-    std::memset((void *)p, 0, sizeof *p);
+    p->timing_mask = (1u << FBL_K_COUNT) - 1u;   // documented default: every kernel
     p->device = -1;
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) {
@@ -309,6 +328,7 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
     G.np = g->nu * g->nv;
 
     std::vector<ColParam> col((size_t)g->n_views * (size_t)g->nu);
+    std::vector<ColParam64> col64(col.size());
     p->view_axis0 = new unsigned char[g->n_views];
     double tau_max = 0.0, tau_min = 1.0;
     for (int64_t v = 0; v < g->n_views; ++v) {
@@ -337,6 +357,7 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
             const double ex = cg.q[0] - cg.s[0], ey = cg.q[1] - cg.s[1];
             cp.wa = (float)(ha / std::fabs(cg.q[a] - cg.s[a]));
             cp.l2 = (float)(ex * ex + ey * ey);
+            col64[(size_t)v * (size_t)g->nu + (size_t)iu] = ColParam64{ha / std::fabs(cg.q[a] - cg.s[a]), ex * ex + ey * ey};
             cp.axis = a;
             cp.pad = 0;
         }
@@ -353,7 +374,7 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
             if (p->fp_line == 0 && need <= (double)sz) p->fp_line = sz;
         if (p->fp_line == 0) {
             free_plan(p);
-            return fail(FBL_E_GEOMETRY,
+            return set_error(FBL_E_GEOMETRY,
                         "detector rows are too coarse for the voxel size: %d rows span %.1f voxels in z (max 45)",
                         forward_rows_per_thread(), span);
         }
@@ -373,7 +394,7 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
             }
         if (changes > 1) {
             free_plan(p);
-            return fail(FBL_E_GEOMETRY, "view %lld: the detector row changes dominant axis %d times (fan too wide)",
+            return set_error(FBL_E_GEOMETRY, "view %lld: the detector row changes dominant axis %d times (fan too wide)",
                         (long long)v, changes);
         }
         vp[(size_t)v].axis_first = cv[0].axis;
@@ -390,7 +411,7 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
         p->bp_cand = cand <= 3.0 ? 3 : cand <= 4.0 ? 4 : cand <= 5.0 ? 5 : cand <= 6.0 ? 6 : cand <= 8.0 ? 8 : 0;
         if (p->bp_cand == 0) {
             free_plan(p);
-            return fail(FBL_E_GEOMETRY, "detector rows are too fine for the voxel size (%.3f voxels apart, min 0.34)",
+            return set_error(FBL_E_GEOMETRY, "detector rows are too fine for the voxel size (%.3f voxels apart, min 0.34)",
                         rowz_min);
         }
         const int TQ = backproject_tile();
@@ -439,7 +460,7 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
             if (p->bp_pairs == 0 && need <= sz) p->bp_pairs = sz;
         if (p->bp_pairs == 0) {
             free_plan(p);
-            return fail(FBL_E_GEOMETRY,
+            return set_error(FBL_E_GEOMETRY,
                         "detector columns are too fine for the voxel size: %d columns cross one %d-voxel tile slice",
                         max_n, TQ);
         }
@@ -476,7 +497,8 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
     const int64_t np_step = 3 * (int64_t)step_blocks(p);
     p->n_partials = np_fp > np_step ? np_fp : np_step;
 
-    if ((rc = dev_upload(&p->d_col, col)) != FBL_OK || (rc = dev_upload(&p->d_rowV, rowV)) != FBL_OK ||
+    if ((rc = dev_upload(&p->d_col, col)) != FBL_OK || (rc = dev_upload(&p->d_col64, col64)) != FBL_OK ||
+        (rc = dev_upload(&p->d_rowV, rowV)) != FBL_OK ||
         (rc = dev_upload(&p->d_rowV2, rowV2)) != FBL_OK || (rc = dev_upload(&p->d_view, vp)) != FBL_OK ||
         (rc = dev_upload(&p->d_bp_order, bp_order)) != FBL_OK) {
         std::string msg = g_err;
@@ -490,7 +512,7 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
         e = hipMalloc(&p->d_xt, (size_t)g->nx * (size_t)g->ny * (size_t)g->nz * (vol_dtype == FBL_F32 ? 4u : 2u));
     if (e != hipSuccess) {
         free_plan(p);
-        return fail(FBL_E_NOMEM, "hipMalloc of plan workspace: %s", hipGetErrorString(e));
+        return set_error(FBL_E_NOMEM, "hipMalloc of plan workspace: %s", hipGetErrorString(e));
     }
     *out = p;
     return ok();
@@ -503,10 +525,10 @@ int fb_lisa_forward(fbl_plan *p, const void *x, const int32_t *views, int32_t B,
 {
     int rc = check_call(p, views, B);
     if (rc != FBL_OK) return rc;
-    if (!x || !y) return fail(FBL_E_INVALID, "x and y must be non-NULL");
+    if (!x || !y) return set_error(FBL_E_INVALID, "x and y must be non-NULL");
     if (!aligned16(x) || !aligned16(y) || (b && !aligned16(b)) || (loss_dev && !aligned8(loss_dev)))
-        return fail(FBL_E_INVALID, "arrays must be 16-byte aligned and loss_dev 8-byte aligned");
-    if (loss_dev && !std::isfinite(loss_scale)) return fail(FBL_E_INVALID, "loss_scale must be finite");
+        return set_error(FBL_E_INVALID, "arrays must be 16-byte aligned and loss_dev 8-byte aligned");
+    if (loss_dev && !std::isfinite(loss_scale)) return set_error(FBL_E_INVALID, "loss_scale must be finite");
     hipStream_t st = (hipStream_t)stream;
     bool need_xt = false;
     for (int32_t k = 0; k < B; ++k) need_xt = need_xt || p->view_axis0[views[k]];
@@ -538,9 +560,9 @@ int fb_lisa_backproject(fbl_plan *p, const float *r, const int32_t *views, int32
 {
     int rc = check_call(p, views, B);
     if (rc != FBL_OK) return rc;
-    if (!r || !g) return fail(FBL_E_INVALID, "r and g must be non-NULL");
-    if (!aligned16(r) || !aligned16(g)) return fail(FBL_E_INVALID, "device buffers must be 16-byte aligned");
-    if (!std::isfinite(grad_scale)) return fail(FBL_E_INVALID, "grad_scale must be finite");
+    if (!r || !g) return set_error(FBL_E_INVALID, "r and g must be non-NULL");
+    if (!aligned16(r) || !aligned16(g)) return set_error(FBL_E_INVALID, "device buffers must be 16-byte aligned");
+    if (!std::isfinite(grad_scale)) return set_error(FBL_E_INVALID, "grad_scale must be finite");
     hipStream_t st = (hipStream_t)stream;
     for (int first = 0; first < B; first += kViewsPerLaunch) {
         const int nb = B - first < kViewsPerLaunch ? B - first : kViewsPerLaunch;
@@ -560,10 +582,67 @@ int fb_lisa_backproject(fbl_plan *p, const float *r, const int32_t *views, int32
 }
 
 
+int fb_lisa_forward_f64(fbl_plan *p, const double *x, const int32_t *views, int32_t B, double *y, void *stream)
+{
+    int rc = check_call(p, views, B);
+    if (rc != FBL_OK) return rc;
+    if (!x || !y) return set_error(FBL_E_INVALID, "x and y must be non-NULL");
+    if (!aligned16(x) || !aligned16(y)) return set_error(FBL_E_INVALID, "arrays must be 16-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    for (int first = 0; first < B; first += kViewsPerLaunch) {
+        const int nb = B - first < kViewsPerLaunch ? B - first : kViewsPerLaunch;
+        const ViewList vl = chunk(views, first, nb);
+        hipError_t e = launch_forward64(p, x, vl, nb, y + (int64_t)first * p->geo.np, st);
+        if (e != hipSuccess) return hip_fail(e, "FP64 forward projection launch");
+    }
+    return ok();
+}
+
+int fb_lisa_backproject_f64(fbl_plan *p, const double *r, const int32_t *views, int32_t B, double grad_scale,
+                            double *g, void *stream)
+{
+    int rc = check_call(p, views, B);
+    if (rc != FBL_OK) return rc;
+    if (!r || !g) return set_error(FBL_E_INVALID, "r and g must be non-NULL");
+    if (!aligned16(r) || !aligned16(g)) return set_error(FBL_E_INVALID, "arrays must be 16-byte aligned");
+    if (!std::isfinite(grad_scale)) return set_error(FBL_E_INVALID, "grad_scale must be finite");
+    hipStream_t st = (hipStream_t)stream;
+    for (int first = 0; first < B; first += kViewsPerLaunch) {
+        const int nb = B - first < kViewsPerLaunch ? B - first : kViewsPerLaunch;
+        const ViewList vl = chunk(views, first, nb);
+        hipError_t e = launch_backproject64(p, r + (int64_t)first * p->geo.np, vl, nb, grad_scale, first > 0, g, st);
+        if (e != hipSuccess) return hip_fail(e, "FP64 backprojection launch");
+    }
+    return ok();
+}
+
 int fb_lisa_step(fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo, double hi, void *xbar,
                  double *red_dev, void *stream)
 {
     return step_call(p, x, g, alpha, mu, lo, hi, false, 0, xbar, red_dev, stream);
+}
+
+int fb_lisa_step_mixed(fbl_plan *p, const float *x, const float *g, double alpha, double mu, double lo, double hi,
+                       float *xbar, void *xbar16, double *red_dev, void *stream)
+{
+    if (!p) return set_error(FBL_E_INVALID, "plan is NULL");
+    if (p->vol_dtype == FBL_F32)
+        return set_error(FBL_E_DTYPE, "fb_lisa_step_mixed needs a plan with 16-bit volume storage (BF16 or F16)");
+    if (!xbar16) return set_error(FBL_E_INVALID, "xbar16 must be non-NULL");
+    if (!aligned16(xbar16)) return set_error(FBL_E_INVALID, "arrays must be 16-byte aligned");
+    if (xbar16 == (void *)x || xbar16 == (void *)g || xbar16 == (void *)xbar)
+        return set_error(FBL_E_INVALID, "xbar16 may not alias x, g or xbar");
+    int rc = check_step_args(p, x, g, alpha, mu, lo, hi, xbar, red_dev);
+    if (rc != FBL_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    int64_t nparts = 0;
+    hipError_t e = timed(p, FBL_K_STEP, st, [&] {
+        return launch_step_mixed(p, x, g, alpha, mu, lo, hi, xbar, xbar16, &nparts, st);
+    });
+    if (e != hipSuccess) return hip_fail(e, "mixed step launch");
+    e = timed(p, FBL_K_FINALIZE, st, [&] { return launch_finalize_sum(p->d_partials, nparts, 3, 1.0, red_dev, st); });
+    if (e != hipSuccess) return hip_fail(e, "step reduction launch");
+    return ok();
 }
 
 int fb_lisa_step_sr(fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo, double hi,
@@ -576,10 +655,10 @@ size_t fbl_mlp_workspace_bytes(int64_t n) { return n < 1 ? 0 : mlp_workspace_byt
 
 int fbl_mlp_forward(const float *params, const float *X, int64_t n, float *out, void *stream)
 {
-    if (!params || !X || !out) return fail(FBL_E_INVALID, "params, X and out must be non-NULL");
-    if (n < 1 || n > ((int64_t)1 << 31)) return fail(FBL_E_RANGE, "n = %lld outside [1, 2^31]", (long long)n);
+    if (!params || !X || !out) return set_error(FBL_E_INVALID, "params, X and out must be non-NULL");
+    if (n < 1 || n > ((int64_t)1 << 31)) return set_error(FBL_E_RANGE, "n = %lld outside [1, 2^31]", (long long)n);
     if (!aligned16(params) || !aligned16(X) || !aligned16(out))
-        return fail(FBL_E_INVALID, "arrays must be 16-byte aligned");
+        return set_error(FBL_E_INVALID, "arrays must be 16-byte aligned");
     hipError_t e = launch_mlp_forward(params, X, n, out, (hipStream_t)stream);
     return e == hipSuccess ? ok() : hip_fail(e, "MLP forward launch");
 }
@@ -587,11 +666,11 @@ int fbl_mlp_forward(const float *params, const float *X, int64_t n, float *out, 
 int fbl_mlp_loss_grad(const float *params, const float *X, const float *t, int64_t n, float *grad, double *loss_dev,
                       void *work, void *stream)
 {
-    if (!params || !X || !t || !grad || !work) return fail(FBL_E_INVALID, "params, X, t, grad and work must be non-NULL");
-    if (n < 1 || n > ((int64_t)1 << 31)) return fail(FBL_E_RANGE, "n = %lld outside [1, 2^31]", (long long)n);
+    if (!params || !X || !t || !grad || !work) return set_error(FBL_E_INVALID, "params, X, t, grad and work must be non-NULL");
+    if (n < 1 || n > ((int64_t)1 << 31)) return set_error(FBL_E_RANGE, "n = %lld outside [1, 2^31]", (long long)n);
     if (!aligned16(params) || !aligned16(X) || !aligned16(t) || !aligned16(grad) || (loss_dev && !aligned8(loss_dev)))
-        return fail(FBL_E_INVALID, "arrays must be 16-byte aligned and loss_dev 8-byte aligned");
-    if (((uintptr_t)work & 255u) != 0) return fail(FBL_E_INVALID, "work must be 256-byte aligned");
+        return set_error(FBL_E_INVALID, "arrays must be 16-byte aligned and loss_dev 8-byte aligned");
+    if (((uintptr_t)work & 255u) != 0) return set_error(FBL_E_INVALID, "work must be 256-byte aligned");
     hipError_t e = launch_mlp_loss_grad(params, X, t, n, grad, loss_dev, work, (hipStream_t)stream);
     return e == hipSuccess ? ok() : hip_fail(e, "MLP gradient launch");
 }
@@ -599,20 +678,20 @@ int fbl_mlp_loss_grad(const float *params, const float *X, const float *t, int64
 int fbl_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step, double lr, double beta1,
                  double beta2, double eps, void *stream)
 {
-    if (!params || !grad || !m || !v) return fail(FBL_E_INVALID, "params, grad, m and v must be non-NULL");
-    if (step < 1) return fail(FBL_E_RANGE, "step must be >= 1");
+    if (!params || !grad || !m || !v) return set_error(FBL_E_INVALID, "params, grad, m and v must be non-NULL");
+    if (step < 1) return set_error(FBL_E_RANGE, "step must be >= 1");
     if (!(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0) ||
         !std::isfinite(lr) || !std::isfinite(eps))
-        return fail(FBL_E_INVALID, "need lr > 0, 0 <= beta1, beta2 < 1, eps > 0");
+        return set_error(FBL_E_INVALID, "need lr > 0, 0 <= beta1, beta2 < 1, eps > 0");
     if (!aligned16(params) || !aligned16(grad) || !aligned16(m) || !aligned16(v))
-        return fail(FBL_E_INVALID, "arrays must be 16-byte aligned");
+        return set_error(FBL_E_INVALID, "arrays must be 16-byte aligned");
     hipError_t e = launch_mlp_adam(params, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)stream);
     return e == hipSuccess ? ok() : hip_fail(e, "Adam launch");
 }
 
 int fbl_timing_enable(fbl_plan *p, int on)
 {
-    if (!p) return fail(FBL_E_INVALID, "plan is NULL");
+    if (!p) return set_error(FBL_E_INVALID, "plan is NULL");
     if (on) {
         double ms[FBL_K_COUNT];
         int64_t n[FBL_K_COUNT];
@@ -625,15 +704,15 @@ int fbl_timing_enable(fbl_plan *p, int on)
 
 int fbl_timing_select(fbl_plan *p, uint32_t mask)
 {
-    if (!p) return fail(FBL_E_INVALID, "plan is NULL");
-    if (mask >> FBL_K_COUNT) return fail(FBL_E_INVALID, "mask 0x%x has bits beyond FBL_K_COUNT", (unsigned)mask);
+    if (!p) return set_error(FBL_E_INVALID, "plan is NULL");
+    if (mask >> FBL_K_COUNT) return set_error(FBL_E_INVALID, "mask 0x%x has bits beyond FBL_K_COUNT", (unsigned)mask);
     p->timing_mask = mask;
     return ok();
 }
 
 int fbl_timing_read(fbl_plan *p, double ms[FBL_K_COUNT], int64_t launches[FBL_K_COUNT])
 {
-    if (!p || !ms || !launches) return fail(FBL_E_INVALID, "plan, ms and launches must be non-NULL");
+    if (!p || !ms || !launches) return set_error(FBL_E_INVALID, "plan, ms and launches must be non-NULL");
     for (int k = 0; k < FBL_K_COUNT; ++k) {
         ms[k] = 0.0;
         launches[k] = 0;

@@ -86,7 +86,75 @@ __global__ __launch_bounds__(256) void step_kernel(const TV *__restrict__ x, con
     }
 }
 
+// Mixed storage: an FP32 master iterate x (read) and trial point xbar (written), plus a
+// 16-bit copy xbar16 = round-to-nearest(xbar) for the projector to read.  The inner
+// products are those of the FP32 master values.  Four voxels per thread and pass: 16-byte
+// accesses of x, g and xbar, an 8-byte access of xbar16.
+template <typename TS>
+__global__ __launch_bounds__(256) void step_mixed_kernel(const float *__restrict__ x, const float *__restrict__ g,
+                                                         double alpha, double amu, double lo, double hi,
+                                                         float *__restrict__ xbar, TS *__restrict__ xbar16,
+                                                         int64_t d, double *__restrict__ partials)
+{
+#pragma clang fp contract(off)
+    constexpr int V = 4;
+    __shared__ double red[4];
+    double s_inner = 0.0, s_sq = 0.0, s_gg = 0.0;
+    auto trial = [&](float xf, float gf, float &out, TS &out16) {
+        const double xv = (double)xf;
+        const double gv = (double)gf;
+        double v = (xv - alpha * gv) - amu;
+        v = fmin(fmax(v, lo), hi);
+        out = (float)v;
+        out16 = from_f64<TS>((double)out);   // exact input: one rounding to nearest
+        const double dl = (double)out - xv;
+        s_inner += gv * dl;
+        s_sq += dl * dl;
+        s_gg += gv * gv;
+    };
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    const int64_t dv = d / V;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < dv; q += stride) {
+        float xv[V], gv[V], out[V];
+        TS o16[V];
+        load_vec<V>(x, q, xv);
+        load_vec<V>(g, q, gv);
+#pragma unroll
+        for (int k = 0; k < V; ++k) trial(xv[k], gv[k], out[k], o16[k]);
+        store_vec<V>(xbar, q, out);
+        store_vec<V>(xbar16, q, o16);
+    }
+    for (int64_t i = V * dv + (int64_t)blockIdx.x * 256 + threadIdx.x; i < d; i += stride)
+        trial(x[i], g[i], xbar[i], xbar16[i]);
+    const double a = block_sum_256(s_inner, red);
+    const double b = block_sum_256(s_sq, red);
+    const double c = block_sum_256(s_gg, red);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x] = a;
+        partials[3 * blockIdx.x + 1] = b;
+        partials[3 * blockIdx.x + 2] = c;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_step_mixed(const fbl_plan *p, const float *x, const float *g, double alpha, double mu, double lo,
+                             double hi, float *xbar, void *xbar16, int64_t *n_partials_used, hipStream_t st)
+{
+    const int blocks = step_blocks(p);
+    *n_partials_used = blocks;
+    const int64_t d = (int64_t)p->geo.nx * p->geo.ny * p->geo.nz;
+    const double amu = alpha * mu;
+    if (p->vol_dtype == FBL_BF16)
+        hipLaunchKernelGGL(step_mixed_kernel<__hip_bfloat16>, dim3(blocks), dim3(256), 0, st, x, g, alpha, amu, lo,
+                           hi, xbar, (__hip_bfloat16 *)xbar16, d, p->d_partials);
+    else if (p->vol_dtype == FBL_F16)
+        hipLaunchKernelGGL(step_mixed_kernel<__half>, dim3(blocks), dim3(256), 0, st, x, g, alpha, amu, lo, hi,
+                           xbar, (__half *)xbar16, d, p->d_partials);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 int step_blocks(const fbl_plan *p)
 {

@@ -19,7 +19,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import Plan, fb_lisa_backproject, fb_lisa_forward, fb_lisa_step
+from ._lib import Plan, fb_lisa_backproject, fb_lisa_forward, fb_lisa_step, fb_lisa_step_mixed
 
 
 class LineSearchFailed(RuntimeError):
@@ -29,6 +29,12 @@ class LineSearchFailed(RuntimeError):
 def eps_power(k: int, base: float = 0.99) -> float:
     """The summable sequence eps_k = base^k (the paper uses base 0.99)."""
     return math.pow(base, k)
+
+
+def sr_key(seed: int, k: int, j: int) -> int:
+    """Stochastic-rounding key of line-search trial j of iteration k: (seed << 32) +
+    (k << 6) + j modulo 2^64 (j < 64: at most j_max + 1 <= 64 trials)."""
+    return ((int(seed) << 32) + (int(k) << 6) + int(j)) & 0xFFFFFFFFFFFFFFFF
 
 
 def _ceil(z: float) -> int:
@@ -80,13 +86,18 @@ class FBLisa:
     x starts at x0 (default 0).  ``alpha_init(state)`` may propose the first trial step
     of an iteration (default: alpha_0, the paper's reset); the sufficient-decrease test
     and the backtracking still decide on every proposal.
+
+    ``mixed=True`` with a 16-bit ``vol_dtype`` keeps the iterate in FP32 (x, xbar) and
+    gives the projector a 16-bit copy of it (x16, xbar16, written by the prox trial):
+    f and its gradient are evaluated at the copy, the prox step and the inner products
+    of (2.3) on the FP32 values.
     """
 
     def __init__(self, geom, b: torch.Tensor, *, n0: int, epochs: int, alpha0: float = 1e-3, beta: float = 0.5,
                  mu: float = 0.0, lo: float = 0.0, hi: float = math.inf, C: Optional[float] = None,
                  n_max: Optional[int] = None, eps: Callable[[int], float] = eps_power, j_max: int = 50,
                  x0: Optional[torch.Tensor] = None, vol_dtype: str = "f32", proj_dtype: Optional[str] = None,
-                 plan: Optional[Plan] = None, sr_seed: Optional[int] = None):
+                 plan: Optional[Plan] = None, sr_seed: Optional[int] = None, mixed: bool = False):
         self.geom = geom
         self.n = int(geom.n_views)
         self.n0, self.epochs = int(n0), int(epochs)
@@ -102,7 +113,19 @@ class FBLisa:
         self.b = b
         vt = self.plan.vol_torch
         shape = self.plan.vol_shape
-        self.x = torch.zeros(shape, dtype=vt, device=dev) if x0 is None else x0.to(vt).contiguous().clone()
+        self.mixed = bool(mixed)
+        if self.mixed:
+            if vt == torch.float32:
+                raise ValueError("mixed storage needs a 16-bit volume type (vol_dtype 'bf16' or 'f16')")
+            if sr_seed is not None:
+                raise ValueError("mixed storage keeps an FP32 iterate: stochastic rounding does not apply")
+            self.x = (torch.zeros(shape, dtype=torch.float32, device=dev) if x0 is None
+                      else x0.to(torch.float32).contiguous().clone())
+            self.x16 = self.x.to(vt)
+            self.xbar16 = torch.empty_like(self.x16)
+        else:
+            self.x = torch.zeros(shape, dtype=vt, device=dev) if x0 is None else x0.to(vt).contiguous().clone()
+            self.x16 = self.x     # the projector reads the iterate itself
         self.xbar = torch.empty_like(self.x)
         self.g = torch.empty(shape, dtype=torch.float32, device=dev)
         self.r = torch.empty((self.n_max, geom.nv, geom.nu), dtype=torch.float32, device=dev)
@@ -133,7 +156,7 @@ class FBLisa:
         f_scale = self.n / (2.0 * B)
         r, rbar = self.r[:B], self.rbar[:B]
         plan = self.plan
-        fb_lisa_forward(plan, self.x, v, self.b, r, self.scal[0:1], f_scale)
+        fb_lisa_forward(plan, self.x16, v, self.b, r, self.scal[0:1], f_scale)
         fb_lisa_backproject(plan, r, v, self.n / float(B), self.g)
         if callable(alpha_init):
             alpha_init = alpha_init(self)
@@ -143,10 +166,15 @@ class FBLisa:
         trials: List[Trial] = []
         stream = torch.cuda.current_stream()
         for j in range(self.j_max + 1):
-            key = None if self.sr_seed is None else (((int(self.sr_seed) << 32) + (self.k << 6) + j)
-                                                     & 0xFFFFFFFFFFFFFFFF)
-            fb_lisa_step(plan, self.x, self.g, alpha, self.mu, self.lo, self.hi, self.xbar, self.scal[4:7], key=key)
-            fb_lisa_forward(plan, self.xbar, v, self.b, rbar, self.scal[2:3], f_scale)
+            key = None if self.sr_seed is None else sr_key(self.sr_seed, self.k, j)
+            if self.mixed:
+                fb_lisa_step_mixed(plan, self.x, self.g, alpha, self.mu, self.lo, self.hi, self.xbar, self.xbar16,
+                                   self.scal[4:7])
+                fb_lisa_forward(plan, self.xbar16, v, self.b, rbar, self.scal[2:3], f_scale)
+            else:
+                fb_lisa_step(plan, self.x, self.g, alpha, self.mu, self.lo, self.hi, self.xbar, self.scal[4:7],
+                             key=key)
+                fb_lisa_forward(plan, self.xbar, v, self.b, rbar, self.scal[2:3], f_scale)
             self.host.copy_(self.scal, non_blocking=True)
             stream.synchronize()
             h = self.host.tolist()
@@ -166,6 +194,10 @@ class FBLisa:
                                    % (self.j_max + 1, self.k))
         # Step 2d: accept (swap buffers; x keeps the accepted trial point)
         self.x, self.xbar = self.xbar, self.x
+        if self.mixed:
+            self.x16, self.xbar16 = self.xbar16, self.x16
+        else:
+            self.x16 = self.x
         it = Iteration(epoch, self.k, v.copy(), f0, alpha, len(trials) - 1, gnorm, trials,
                        time.perf_counter() - t0)
         self.history.append(it)

@@ -18,7 +18,7 @@ def bench(tmp_path):
     spec.loader.exec_module(mod)
     csrc = tmp_path / "paper_2605_12085_amd" / "csrc"
     csrc.mkdir(parents=True)
-    for f in ("forward.hip", "backproject.hip", "device_util.h"):
+    for f in ("forward.hip", "backproject.hip", "device_util.h", "common.h", "plan.hip"):
         shutil.copy(os.path.join(ROOT, "paper_2605_12085_amd", "csrc", f), csrc / f)
     (tmp_path / "profiles").mkdir()
     mod.ROOT = str(tmp_path)
@@ -36,10 +36,12 @@ def test_hash_ignores_comments_and_spacing(bench):
     assert mod.kernel_source_hash("fp_kernel") != h0
 
 
-def test_hash_covers_the_shared_device_helpers(bench):
+@pytest.mark.parametrize("shared", ["device_util.h", "common.h", "plan.hip"])
+def test_hash_covers_the_shared_sources(bench, shared):
+    # device helpers, shared declarations and the host code that picks launch shapes
     mod, root = bench
     h_fp, h_bp = mod.kernel_source_hash("fp_kernel"), mod.kernel_source_hash("bp_kernel")
-    p = root / "paper_2605_12085_amd" / "csrc" / "device_util.h"
+    p = root / "paper_2605_12085_amd" / "csrc" / shared
     p.write_text(p.read_text() + "\nnamespace fbl { constexpr int kUnused = 1; }\n")
     assert mod.kernel_source_hash("fp_kernel") != h_fp
     assert mod.kernel_source_hash("bp_kernel") != h_bp

@@ -1,14 +1,15 @@
 """The projector pair as torch.autograd functions (HIP kernels through the C ABI).
 
-Checks: torch.autograd.gradcheck of both directions on an 8^3 volume (finite differences
-with eps 1e-3, Jacobians compared in FP64); second derivatives (A^T A v); a directional
-finite difference of the mini-batch objective at 128^3 with 180 views (the objective is
-quadratic, so the central difference is exact up to rounding); the adjoint dot-product
-identity through vector-Jacobian products; and the gradient against the FP64 oracle.
-
-The kernels compute in FP32, so the finite-difference Jacobian carries the FP32 rounding
-of the outputs divided by 2*eps (about 1e-6 / 2e-3): the gradcheck tolerance is
-atol 2e-3 on entries of size ~1, rtol 1e-3.
+Checks: torch.autograd.gradcheck of both directions on 8^3 and 16^3 volumes in true FP64
+(the library's FP64 instantiation of the pair; finite differences with eps 1e-3 are
+exact up to FP64 rounding for a linear map, so the tolerance is atol 1e-9); the same
+gradcheck through the FP32 kernels, whose finite-difference Jacobian carries the FP32
+rounding of the outputs divided by 2*eps (about 1e-6 / 2e-3), hence atol 2e-3, rtol
+1e-3 there; second derivatives (A^T A v); a directional finite difference of the
+mini-batch objective at 128^3 with 180 views (the objective is quadratic, so the central
+difference is exact up to rounding); the adjoint dot-product identity through
+vector-Jacobian products; the gradient against the FP64 oracle; and the FP64 pair itself
+against the oracle to 1e-12.
 """
 import numpy as np
 import pytest
@@ -26,10 +27,33 @@ def fbl():
     return fbl
 
 
-def test_gradcheck_project_and_backproject(fbl):
+@pytest.mark.parametrize("n,det", [(8, 12), (16, 20)])
+def test_gradcheck_fp64_project_and_backproject(fbl, n, det):
+    # true FP64: FP64 tensors run the FP64 instantiation of the pair in both directions
+    import torch
+    g = syn.tiny_geometry(n=n, det=det, views=16)
+    views = [0, 3, 6, 13]   # both axis classes
+    rng = np.random.default_rng(7)
+    with fbl.Plan(g) as plan:
+        x = torch.tensor(rng.uniform(0, 1, g.vol_shape), dtype=torch.float64, device="cuda", requires_grad=True)
+        r = torch.tensor(rng.standard_normal((len(views), g.nv, g.nu)), dtype=torch.float64, device="cuda",
+                         requires_grad=True)
+        fp = lambda t: fbl.project(t, plan, views)
+        bp = lambda t: fbl.backproject(t, plan, views)
+        assert fp(x).dtype == torch.float64
+        # the FP64 transpose adds with atomics, so repeated backward calls may differ by
+        # FP64 rounding: nondet_tol admits that and nothing larger
+        assert torch.autograd.gradcheck(fp, (x,), eps=1e-3, atol=1e-9, rtol=1e-7, nondet_tol=1e-12,
+                                        fast_mode=n > 8)
+        assert torch.autograd.gradcheck(bp, (r,), eps=1e-3, atol=1e-9, rtol=1e-7, nondet_tol=1e-12,
+                                        fast_mode=n > 8)
+
+
+def test_gradcheck_fp32_project_and_backproject(fbl):
+    # the fast FP32 kernels, checked at the FP32 resolution of the finite differences
     import torch
     g = syn.tiny_geometry(n=8, det=12, views=16)
-    views = [0, 3, 6, 13]   # both axis classes
+    views = [0, 3, 6, 13]
     rng = np.random.default_rng(7)
     with fbl.Plan(g) as plan:
         x = torch.tensor(rng.uniform(0, 1, g.vol_shape), dtype=torch.float64, device="cuda", requires_grad=True)
@@ -39,6 +63,35 @@ def test_gradcheck_project_and_backproject(fbl):
         bp = lambda t: fbl.backproject(t.float(), plan, views).double()
         assert torch.autograd.gradcheck(fp, (x,), eps=1e-3, atol=2e-3, rtol=1e-3, fast_mode=False)
         assert torch.autograd.gradcheck(bp, (r,), eps=1e-3, atol=2e-3, rtol=1e-3, fast_mode=False)
+
+
+def test_fp64_pair_matches_oracle(fbl, orc):
+    # the FP64 instantiation against the FP64 oracle: equal up to FP64 rounding (1e-12),
+    # on odd sizes with axis-aligned and oblique views, both directions
+    import torch
+    g = syn.Geometry(29, 41, 37, 0.9, 1.1, 1.0, 50, 33, 1.7, 1.9, 400.0, 900.0, 12,
+                     angles=[0.0, np.pi / 4, np.pi / 2, np.pi, 3 * np.pi / 2, 0.3, 1.7, 2.9, 4.0, 5.5, 0.05, 6.2])
+    views = np.arange(g.n_views, dtype=np.int32)
+    rng = np.random.default_rng(31)
+    x = rng.uniform(-1, 1, g.vol_shape)
+    r = rng.standard_normal((g.n_views, g.nv, g.nu))
+    y_ref = orc.forward(g, x, views)
+    g_ref = orc.backproject(g, r, views)
+    with fbl.Plan(g) as plan:
+        y = fbl.fb_lisa_forward_f64(plan, torch.from_numpy(x).cuda(), views).cpu().numpy()
+        gg = fbl.fb_lisa_backproject_f64(plan, torch.from_numpy(r).cuda(), views, grad_scale=1.0).cpu().numpy()
+        # the gradient scale, and repeated views in one batch
+        vv = np.array([0, 0, 3, 7, 7, 11], dtype=np.int32)
+        rr = rng.standard_normal((len(vv), g.nv, g.nu))
+        g2 = fbl.fb_lisa_backproject_f64(plan, torch.from_numpy(rr).cuda(), vv, grad_scale=0.5).cpu().numpy()
+    for b in range(g.n_views):
+        assert np.abs(y[b] - y_ref[b]).max() <= 1e-12 * np.abs(y_ref[b]).max(), b
+    assert np.abs(gg - g_ref).max() <= 1e-12 * np.abs(g_ref).max()
+    g2_ref = 0.5 * orc.backproject(g, rr, vv)
+    assert np.abs(g2 - g2_ref).max() <= 1e-12 * np.abs(g2_ref).max()
+    # adjoint identity in FP64
+    lhs, rhs = float(np.sum(y * r)), float(np.sum(x * gg))
+    assert lhs == pytest.approx(rhs, rel=1e-13)
 
 
 def test_second_derivative_is_normal_operator(fbl):

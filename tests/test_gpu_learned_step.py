@@ -152,10 +152,14 @@ def test_learned_step_gain(fbl, capsys):
         bl = np.mean([r["backtracks"] for r in learned])
         fp = np.mean([r["fp_per_iter"] for r in plain])
         fl = np.mean([r["fp_per_iter"] for r in learned])
-        # the proposer errs towards larger steps (a rejected proposal costs one trial), so
-        # the gain is bounded by one trial per iteration: at least a fifth of the forward
-        # projections and half the backtracks go, with no loss of accuracy
-        assert bl <= 0.6 * bp, (name, bl, bp)
+        # The proposal is the predicted halving count rounded down, so even an exact
+        # predictor may leave one rejected trial per iteration: the floor of the method is
+        # up to one backtrack, i.e. 3 forward calls per iteration against the plain run's
+        # 2 + bp.  The bars: at most one backtrack per iteration, at most half the plain
+        # run's backtracks, and (what the first implies at these plain counts) at most
+        # four fifths of its forward projections, with no loss of accuracy.
+        assert bl <= 1.0, (name, bl)
+        assert bl <= 0.5 * bp, (name, bl, bp)
         assert fl <= 0.8 * fp, (name, fl, fp)
         for p_, l_ in zip(plain, learned):
             assert l_["rmse"] <= 1.02 * p_["rmse"], (name, l_["rmse"], p_["rmse"])

@@ -385,6 +385,100 @@ def test_launch_timing_records_every_kernel(fbl):
         torch.cuda.synchronize()
 
 
+def test_timing_default_selects_every_kernel(fbl):
+    # through the C ABI with no fbl_timing_select: the documented default brackets every
+    # kernel the calls launch
+    import ctypes
+    import torch
+    from paper_2605_12085_amd import _lib
+    g = syn.tiny_geometry(n=8, det=12, views=16)
+    x = _t(syn.random_volume(g, seed=3).astype(np.float32))
+    b = torch.zeros((g.n_views, g.nv, g.nu), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with fbl.Plan(g) as plan:
+        _lib._check(_lib.lib.fbl_timing_enable(plan.handle, 1))
+        views = list(range(g.n_views))
+        r = fbl.fb_lisa_forward(plan, x, views, b, loss=loss)
+        gr = fbl.fb_lisa_backproject(plan, r, views)
+        fbl.fb_lisa_step(plan, x, gr, 1e-3)
+        ms = (ctypes.c_double * len(_lib.KERNELS))()
+        n = (ctypes.c_int64 * len(_lib.KERNELS))()
+        _lib._check(_lib.lib.fbl_timing_read(plan.handle, ms, n))
+        _lib._check(_lib.lib.fbl_timing_enable(plan.handle, 0))
+        assert dict(zip(_lib.KERNELS, list(n))) == {"forward": 1, "transpose": 1, "finalize": 2, "prescale": 1,
+                                                     "backproject": 1, "step": 1}
+        assert all(v > 0 for v in ms)
+        torch.cuda.synchronize()
+
+
+def _forward_line_entries(g, rows_per_thread=16):
+    """The forward's per-thread line length for a geometry, from the plan's rule: the
+    z-span of 16 rows on the slice farthest from the source, plus three entries."""
+    taus = []
+    for v in range(g.n_views):
+        th = g.angles[v]
+        c, s = math.cos(th), math.sin(th)
+        for iu in range(g.nu):
+            u = (iu - 0.5 * (g.nu - 1)) * g.du
+            src = np.array([g.sod * c, g.sod * s])
+            q = np.array([(g.sod - g.sdd) * c - u * s, (g.sod - g.sdd) * s + u * c])
+            h = np.array([g.hx, g.hy])
+            n = np.array([g.nx, g.ny])
+            P, D = src / h + 0.5 * (n - 1), (q - src) / h
+            a = 0 if abs(D[0]) >= abs(D[1]) else 1
+            taus += [(0.0 - P[a]) / D[a], (n[a] - 1.0 - P[a]) / D[a]]
+    span = max(taus) * (rows_per_thread - 1) * (g.dv / g.hz)
+    need = math.floor(span + 0.01) + 3
+    return next(sz for sz in (12, 16, 24, 32, 48) if need <= sz)
+
+
+@pytest.mark.parametrize("dv,kb", [(3.2, 32), (4.8, 48)])
+def test_coarse_detector_rows_long_forward_lines(fbl, orc, dv, kb):
+    # detector rows 1.6-2.4 voxels apart at the volume: a thread's 16 rows span 25-37
+    # voxels in z, which selects the forward's 32- and 48-entry line buffers
+    g = syn.Geometry(24, 24, 20, 1.0, 1.0, 1.0, 36, 12, 1.5, dv, 300.0, 600.0, 12)
+    assert _forward_line_entries(g) == kb
+    rng = np.random.default_rng(40 + kb)
+    views = np.arange(g.n_views, dtype=np.int32)
+    x = rng.uniform(0, 1, g.vol_shape).astype(np.float32)
+    r = rng.standard_normal((len(views), g.nv, g.nu)).astype(np.float32)
+    y_ref = orc.forward(g, x.astype(np.float64), views)
+    g_ref = orc.backproject(g, r.astype(np.float64), views)
+    with fbl.Plan(g) as plan:
+        y = fbl.fb_lisa_forward(plan, _t(x), views).cpu().numpy()
+        gg = fbl.fb_lisa_backproject(plan, _t(r), views, grad_scale=1.0).cpu().numpy()
+    _cmp_views(y, y_ref, what="forward, %d-entry lines" % kb)
+    _cmp_vol(gg, g_ref, what="backprojection, coarse rows")
+
+
+def test_exact_dominant_axis_tie(fbl, orc):
+    # theta = 0, isotropic voxels, outermost columns at u = +-SDD: their rays run at 45
+    # degrees, |D_x| = |D_y| exactly in FP64, and the tie goes to x on both sides.  SOD is
+    # small enough (18 mm for a 20 mm volume) that these rays cross the volume's corners.
+    g = syn.Geometry(20, 20, 4, 1.0, 1.0, 1.0, 5, 6, 18.0, 2.0, 18.0, 36.0, 1, angles=[0.0])
+    views = np.array([0], dtype=np.int32)
+    for iu in (0, 4):
+        u = (iu - 2) * 18.0
+        dx, dy = (-18.0 - 18.0) / 1.0, u / 1.0
+        assert abs(dx) == abs(dy)
+    axes = orc.dominant_axes(g, 0)
+    assert np.all(axes == 0)
+    rng = np.random.default_rng(44)
+    x = rng.uniform(0, 1, g.vol_shape).astype(np.float32)
+    r = rng.standard_normal((1, g.nv, g.nu)).astype(np.float32)
+    y_ref = orc.forward(g, x.astype(np.float64), views)
+    assert np.all(y_ref[0][:, [0, 4]] > 0)   # the tie rays cross the volume
+    g_ref = orc.backproject(g, r.astype(np.float64), views)
+    with fbl.Plan(g) as plan:
+        y = fbl.fb_lisa_forward(plan, _t(x), views).cpu().numpy()
+        gg = fbl.fb_lisa_backproject(plan, _t(r), views, grad_scale=1.0).cpu().numpy()
+    _cmp_views(y, y_ref, what="forward, exact axis tie")
+    for iu in (0, 4):
+        col = y[0][:, iu].astype(np.float64)
+        assert np.abs(col - y_ref[0][:, iu]).max() <= TOL * np.abs(y_ref[0][:, iu]).max()
+    _cmp_vol(gg, g_ref, what="backprojection, exact axis tie")
+
+
 @pytest.mark.parametrize("cfg", ["c2", "c3", "c5"])
 def test_full_size_sampled_parity(fbl, orc, cfg):
     # Full-size geometry and the batch size the benchmark times; rays and voxels are
@@ -420,9 +514,15 @@ def test_full_size_sampled_parity(fbl, orc, cfg):
     assert np.linalg.norm(got - ref) <= TOL * np.linalg.norm(ref)
     # voxels: inside the field of view and at the volume's edges and corners (the oracle
     # sums over every ray of the batch per voxel, so fewer are taken at the larger sizes)
-    nvx = {"c2": 96, "c3": 48, "c5": 16}[cfg]
+    nvx = {"c2": 96, "c3": 64, "c5": 64}[cfg]
     vox = rng.integers(0, g.d, nvx)
     vox[:8] = [0, g.nx - 1, g.nx * (g.ny - 1), g.d - 1, g.d // 2, g.d // 2 + 1, g.d // 2 + g.nx, g.d // 3]
+    # near the rotation axis at the top and bottom of the volume, where the rows reaching a
+    # backprojection tile span the tallest windows, and at tile boundaries in z
+    cx, cy = g.nx // 2, g.ny // 2
+    for n_, (k, dx, dy) in enumerate([(0, 0, 0), (1, 5, -7), (15, -3, 2), (16, 9, 4),
+                                      (g.nz - 17, 1, 1), (g.nz - 16, -6, 8), (g.nz - 2, 2, -2), (g.nz - 1, -1, 0)]):
+        vox[8 + n_] = (cx + dx) + g.nx * ((cy + dy) + g.ny * k)
     gref = orc.backproject_voxels(g, r.astype(np.float64), views, vox)
     ggot = gg.reshape(-1)[vox].astype(np.float64)
     gscale = np.abs(gref).max()

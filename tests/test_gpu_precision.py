@@ -254,3 +254,88 @@ def test_bf16_stochastic_iterates_replay(fbl, orc, capsys):
         print("\nbf16 iterates, stochastic rounding: RE vs FP64 run %.3e; RMSE vs phantom %.4e (FP64 %.4e)"
               % (orc.relative_error(xs_g[-1], x64), orc.rmse(xs_g[-1], xt), orc.rmse(x64, xt)), flush=True)
     assert orc.relative_error(xs_g[-1], x64) <= 4 * U["bf16"]
+
+
+@pytest.mark.parametrize("st", ["bf16", "f16"])
+@pytest.mark.parametrize("shape", ["odd", "128"])
+def test_step_mixed_master_and_copy(fbl, orc, st, shape):
+    """Mixed storage: the FP32 trial point is the oracle's FP64 prox rounded once to FP32
+    (within one FP32 ulp, > 99.9% identical), its 16-bit copy is exactly the nearest
+    rounding of the returned FP32 value, and the inner products are those of the FP32
+    values ("odd": a tail of one after the four-voxel passes; "128": several grid-stride
+    passes per thread)."""
+    import torch
+    g = ODD if shape == "odd" else syn.config_geometry("c4")
+    settings = ((1e-3, 0.0, 0.0, math.inf), (2.5e-3, 0.7, 0.0, 0.03), (1e-4, 2.0, 0.001, 0.025))
+    if shape == "128":
+        settings = settings[1:2]
+    rng = np.random.default_rng(24)
+    x32 = rng.uniform(0, 0.03, g.vol_shape).astype(np.float32)
+    x32[rng.random(g.vol_shape) < 0.2] = 0.0
+    grad = (rng.standard_normal(g.vol_shape) * 3.0).astype(np.float32)
+    with fbl.Plan(g, vol_dtype=st) as plan:
+        for alpha, mu, lo, hi in settings:
+            red = torch.zeros(3, dtype=torch.float64, device="cuda")
+            xb, xb16, red = fbl.fb_lisa_step_mixed(plan, torch.from_numpy(x32).cuda(), torch.from_numpy(grad).cuda(),
+                                                   alpha, mu, lo, hi, red=red)
+            xb = xb.cpu().numpy().astype(np.float64)
+            xb16 = xb16.to(torch.float64).cpu().numpy()
+            red = red.cpu().numpy()
+            xr, inner, sq, gg = orc.prox_step(x32, grad, alpha, mu, lo, hi, storage="f32")
+            assert np.all(np.abs(xb - xr) <= _storage_ulp(xr, "f32"))
+            assert np.mean(xb == xr) > 0.999
+            assert np.array_equal(xb16, orc.round_storage(xb, st))
+            assert np.mean(xb16 == orc.round_storage(xr, st)) > 0.999
+            assert red[0] == pytest.approx(inner, rel=1e-9)
+            assert red[1] == pytest.approx(sq, rel=1e-9)
+            assert red[2] == pytest.approx(gg, rel=1e-12)
+
+
+def test_step_mixed_rejects_fp32_plan(fbl):
+    import torch
+    g = ODD
+    with fbl.Plan(g) as plan:
+        x = torch.zeros(g.vol_shape, dtype=torch.float32, device="cuda")
+        with pytest.raises(fbl.FblError) as ei:
+            fbl.fb_lisa_step_mixed(plan, x, x.clone(), 1e-3, xbar16=torch.zeros(g.vol_shape, dtype=torch.float32,
+                                                                                 device="cuda"))
+        assert ei.value.code == 4   # FBL_E_DTYPE
+
+
+@pytest.mark.parametrize("st", ["bf16", "f16"])
+def test_mixed_iterates_replay_and_error_against_fp64(fbl, orc, st, capsys):
+    """FB-LISA with an FP32 iterate and a 16-bit copy for the projector.  Replay: the GPU
+    follows the decisions of the oracle's mixed run; its FP32 iterates stay within the
+    16-bit unit roundoff (relative l2) of the oracle's (the FP32 gradient can move a value
+    across a 16-bit rounding boundary, which changes the copy the next gradient sees).
+    Against the FP64 run the error stays at a few unit roundoffs of the copy's type."""
+    import torch
+    g, xt, b32, perms = _loop_problem()
+    epochs, n0 = 2, 4
+    b64 = b32.astype(np.float64)
+    x64, _ = orc.fblisa(g, b64, epochs=epochs, n0=n0, perms=perms)
+    xs_o = []
+    xo, rec = orc.fblisa(g, b64, epochs=epochs, n0=n0, perms=perms, copy_storage=st,
+                         callback=lambda k, x, r: xs_o.append(x.copy()))
+    assert all(np.array_equal(orc.round_storage(x, "f32"), x) for x in xs_o)
+    decisions = [[t.accepted for t in r.trials] for r in rec]
+    bd = torch.from_numpy(b32).cuda()
+    xs_g = []
+    run = fbl.FBLisa(g, bd, n0=n0, epochs=epochs, vol_dtype=st, mixed=True)
+    run.run(perms, decisions=decisions, callback=lambda s, it: xs_g.append(s.x.double().cpu().numpy()))
+    assert len(xs_g) == len(xs_o)
+    worst = 0.0
+    for k, (a, b) in enumerate(zip(xs_g, xs_o)):
+        e = np.linalg.norm(a - b) / np.linalg.norm(b)
+        worst = max(worst, e)
+        assert e <= U[st], (k, e)
+    # the copy the projector reads is the nearest rounding of the iterate
+    assert torch.equal(run.x16, run.x.to(run.x16.dtype))
+    free = fbl.FBLisa(g, bd, n0=n0, epochs=epochs, vol_dtype=st, mixed=True)
+    xf = free.run(perms).double().cpu().numpy()
+    re_m = orc.relative_error(xf, x64)
+    with capsys.disabled():
+        print("\n%s copy of an FP32 iterate: replay worst RE vs oracle %.3e; free run RE vs FP64 run %.3e; "
+              "RMSE vs phantom %.4e (FP64 run %.4e)" % (st, worst, re_m, orc.rmse(xf, xt), orc.rmse(x64, xt)),
+              flush=True)
+    assert re_m <= 4 * U[st]

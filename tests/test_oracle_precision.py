@@ -119,3 +119,36 @@ def test_stochastic_rounding_subnormal_quantum(orc):
     r = orc.round_stochastic(v, "f16", key=5)
     assert set(np.unique(r)) == {3.0 * 2.0 ** -24, 4.0 * 2.0 ** -24}
     assert abs(np.mean(r == 4.0 * 2.0 ** -24) - 0.25) < 0.01
+
+
+def test_mixed_form_by_explicit_matrix(orc):
+    """The mixed form of the loop (FP32 iterates, objective and gradient at their 16-bit
+    copies), checked step by step against the explicit 4^3 matrix: every recorded f(x_k)
+    equals n/(2B) ||A_S bf16(x_k) - b_S||^2 and every accepted iterate equals the FP32
+    rounding of clip(x_k - alpha_k n/B A_S^T (A_S bf16(x_k) - b_S))."""
+    import synthetic as syn
+    g = syn.tiny_geometry(n=4, det=12, views=16, du=0.8)
+    A = orc.assemble_matrix(g, np.arange(g.n_views))
+    rng = np.random.default_rng(5)
+    xt = rng.uniform(0.0, 0.02, g.d)
+    b = (A @ xt + 1e-4 * rng.standard_normal(A.shape[0])).reshape(g.n_views, g.nv, g.nu)
+    perms = np.array([rng.permutation(g.n_views) for _ in range(40)])
+    xs = [np.zeros(g.d)]
+    _, rec = orc.fblisa(g, b, epochs=3, n0=4, perms=perms, copy_storage="bf16",
+                        callback=lambda k, x, r: xs.append(x.ravel().copy()))
+    rows = lambda v: np.concatenate([np.arange(i * g.n_p, (i + 1) * g.n_p) for i in v])
+    rounded_somewhere = False
+    for k, r in enumerate(rec):
+        x = xs[k]
+        xc = orc.round_bf16(x)
+        rounded_somewhere |= not np.array_equal(xc, x)
+        R = rows(r.batch)
+        res = A[R] @ xc - b.ravel()[R]
+        nb = len(r.batch)
+        assert r.f0 == pytest.approx(g.n_views / (2.0 * nb) * float(res @ res), rel=1e-12)
+        grad = g.n_views / nb * (A[R].T @ res)
+        want = np.clip(x - r.alpha * grad, 0.0, np.inf).astype(np.float32).astype(np.float64)
+        ulp = np.spacing(np.abs(want).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(xs[k + 1] - want) <= ulp)
+        assert np.array_equal(xs[k + 1].astype(np.float32).astype(np.float64), xs[k + 1])
+    assert rounded_somewhere
