@@ -234,6 +234,18 @@ FBL_API int fbl_timing_read(fbl_plan *plan, double ms[FBL_K_COUNT], int64_t laun
 FBL_API int fb_lisa_step_sr(fbl_plan *plan, const void *x, const float *g, double alpha, double mu, double lo,
                             double hi, uint64_t key, void *xbar, double *red_dev, void *stream);
 
+/* fb_lisa_step without a plan and without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same operation, rounding to nearest and outputs as fb_lisa_step on
+ * a volume of n_voxels values in vol_dtype (x, xbar; g FP32), n_voxels in [1, 2^31).
+ * Its scratch (FP64 partial sums, at most 2048 blocks x 3) is a 48 KiB array in the
+ * library's device code, one per GPU, held until the process ends; its address is taken
+ * on the first call on each device.  Calls on the same GPU share that array: calls that
+ * overlap in time on one GPU (different streams, or other threads) race and must be
+ * ordered by the caller.  Errors as fb_lisa_step; FBL_E_RANGE for n_voxels out of range. */
+FBL_API int fb_lisa_step_noalloc(int64_t n_voxels, int32_t vol_dtype, const void *x, const float *g, double alpha,
+                                 double mu, double lo, double hi, void *xbar, double *red_dev, void *stream);
+
 /* Message of the last failed call on this thread ("" if none); valid until the next
  * call on the same thread. */
 FBL_API const char *fbl_last_error(void);

@@ -26,7 +26,8 @@ _PROJ_DTYPES = {"f32": (FBL_F32, torch.float32), "bf16": (FBL_BF16, torch.bfloat
 EXPORTED = ("fbl_geometry_check", "fbl_plan_create", "fbl_plan_destroy", "fb_lisa_forward",
             "fb_lisa_backproject", "fb_lisa_step", "fb_lisa_step_sr", "fbl_mlp_workspace_bytes", "fbl_mlp_forward",
             "fbl_mlp_loss_grad", "fbl_mlp_adam", "fbl_timing_enable", "fbl_timing_select", "fbl_timing_read",
-            "fbl_last_error", "fb_lisa_step_mixed", "fb_lisa_forward_f64", "fb_lisa_backproject_f64")
+            "fbl_last_error", "fb_lisa_step_mixed", "fb_lisa_forward_f64", "fb_lisa_backproject_f64",
+            "fb_lisa_step_noalloc")
 MLP_IN, MLP_HIDDEN = 5, 64
 MLP_NPARAMS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 KERNELS = ("forward", "transpose", "finalize", "prescale", "backproject", "step")  # FBL_K_* order
@@ -65,6 +66,8 @@ def _load() -> ctypes.CDLL:
                                     ctypes.c_uint64, P, P, P]
     lib.fb_lisa_step_mixed.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        P, P, P, P]
+    lib.fb_lisa_step_noalloc.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, P, P, P]
     lib.fb_lisa_forward_f64.argtypes = [P, P, P, ctypes.c_int32, P, P]
     lib.fb_lisa_backproject_f64.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_double, P, P]
     lib.fbl_mlp_workspace_bytes.argtypes = [ctypes.c_int64]
@@ -80,7 +83,8 @@ def _load() -> ctypes.CDLL:
     lib.fbl_last_error.restype = ctypes.c_char_p
     for name in ("fbl_geometry_check", "fbl_plan_create", "fb_lisa_forward", "fb_lisa_backproject",
                  "fb_lisa_step", "fb_lisa_step_sr", "fb_lisa_step_mixed", "fb_lisa_forward_f64",
-                 "fb_lisa_backproject_f64", "fbl_mlp_forward", "fbl_mlp_loss_grad", "fbl_mlp_adam",
+                 "fb_lisa_backproject_f64", "fb_lisa_step_noalloc", "fbl_mlp_forward", "fbl_mlp_loss_grad",
+                 "fbl_mlp_adam",
                  "fbl_timing_enable", "fbl_timing_select", "fbl_timing_read"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
@@ -278,6 +282,24 @@ def fb_lisa_step_mixed(plan: Plan, x: torch.Tensor, g: torch.Tensor, alpha: floa
     _check(lib.fb_lisa_step_mixed(plan.handle, x.data_ptr(), g.data_ptr(), float(alpha), float(mu), float(lo),
                                   float(hi), xbar.data_ptr(), xbar16.data_ptr(), red.data_ptr(), _stream(stream)))
     return xbar, xbar16, red
+
+
+def fb_lisa_step_noalloc(x: torch.Tensor, g: torch.Tensor, alpha: float, mu: float, lo: float, hi: float,
+                         xbar: torch.Tensor, red: torch.Tensor, stream=None):
+    """fb_lisa_step without a plan or allocation: x, xbar in one storage type (FP32, BF16 or
+    FP16), g FP32, all of the same number of voxels; red: three FP64 values."""
+    codes = {torch.float32: FBL_F32, torch.bfloat16: FBL_BF16, torch.float16: FBL_F16}
+    if x.dtype not in codes:
+        raise TypeError("x must be float32, bfloat16 or float16")
+    _need(x, "x", x.dtype)
+    _need(xbar, "xbar", x.dtype, tuple(x.shape))
+    _need(g, "g", torch.float32, tuple(x.shape))
+    _need(red, "red", torch.float64)
+    if red.numel() < 3:
+        raise ValueError("red needs three elements")
+    _check(lib.fb_lisa_step_noalloc(x.numel(), codes[x.dtype], x.data_ptr(), g.data_ptr(), float(alpha), float(mu),
+                                    float(lo), float(hi), xbar.data_ptr(), red.data_ptr(), _stream(stream)))
+    return xbar, red
 
 
 def fb_lisa_forward_f64(plan: Plan, x: torch.Tensor, views: Sequence[int], y: Optional[torch.Tensor] = None,

@@ -112,6 +112,11 @@ namespace fbl {
 // message and returns `code`; clear_error empties it and returns FBL_OK.
 int set_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int clear_error();
+// Checks of the prox trial's buffers and scalars shared by its entry points: non-NULL,
+// 16-byte aligned arrays (red_dev 8), xbar not aliasing x or g, alpha > 0, mu >= 0,
+// 0 <= lo <= hi.  Returns FBL_OK or FBL_E_INVALID with the message set.
+int check_step_buffers(const void *x, const float *g, double alpha, double mu, double lo, double hi, const void *xbar,
+                       const double *red_dev);
 
 // Launch functions (stream-ordered, no synchronisation).  Each returns hipSuccess or the
 // launch error.

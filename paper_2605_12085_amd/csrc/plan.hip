@@ -35,6 +35,21 @@ int clear_error()
     return FBL_OK;
 }
 
+int check_step_buffers(const void *x, const float *g, double alpha, double mu, double lo, double hi, const void *xbar,
+                       const double *red_dev)
+{
+    auto al16 = [](const void *q) { return ((uintptr_t)q & 15u) == 0; };
+    if (!x || !g || !xbar || !red_dev) return set_error(FBL_E_INVALID, "x, g, xbar and red_dev must be non-NULL");
+    if (!al16(x) || !al16(g) || !al16(xbar) || ((uintptr_t)red_dev & 7u) != 0)
+        return set_error(FBL_E_INVALID, "arrays must be 16-byte aligned and red_dev 8-byte aligned");
+    if (xbar == x || (const void *)xbar == (const void *)g) return set_error(FBL_E_INVALID, "xbar may not alias x or g");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return set_error(FBL_E_INVALID, "alpha must be finite and > 0");
+    if (!(mu >= 0.0) || !std::isfinite(mu)) return set_error(FBL_E_INVALID, "mu must be finite and >= 0");
+    if (!(lo >= 0.0) || !std::isfinite(lo) || !(hi >= lo))
+        return set_error(FBL_E_INVALID, "bounds must satisfy 0 <= lo <= hi (lo finite)");
+    return FBL_OK;
+}
+
 }  // namespace fbl
 
 namespace {
@@ -239,14 +254,8 @@ ViewList chunk(const int32_t *views, int first, int nb)
 int check_step_args(const fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo, double hi,
                     const void *xbar, const double *red_dev)
 {
-    if (!x || !g || !xbar || !red_dev) return set_error(FBL_E_INVALID, "x, g, xbar and red_dev must be non-NULL");
-    if (!aligned16(x) || !aligned16(g) || !aligned16(xbar) || !aligned8(red_dev))
-        return set_error(FBL_E_INVALID, "arrays must be 16-byte aligned and red_dev 8-byte aligned");
-    if (xbar == x || (const void *)xbar == (const void *)g) return set_error(FBL_E_INVALID, "xbar may not alias x or g");
-    if (!(alpha > 0.0) || !std::isfinite(alpha)) return set_error(FBL_E_INVALID, "alpha must be finite and > 0");
-    if (!(mu >= 0.0) || !std::isfinite(mu)) return set_error(FBL_E_INVALID, "mu must be finite and >= 0");
-    if (!(lo >= 0.0) || !std::isfinite(lo) || !(hi >= lo))
-        return set_error(FBL_E_INVALID, "bounds must satisfy 0 <= lo <= hi (lo finite)");
+    const int rc = check_step_buffers(x, g, alpha, mu, lo, hi, xbar, red_dev);
+    if (rc != FBL_OK) return rc;
     int cur = -1;
     hipError_t e = hipGetDevice(&cur);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");

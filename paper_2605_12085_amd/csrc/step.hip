@@ -1,4 +1,6 @@
 // Prox-gradient trial and the FP64 inner products of the sufficient-decrease test.
+#include <mutex>
+
 #include "common.h"
 #include "device_util.h"
 
@@ -156,31 +158,34 @@ hipError_t launch_step_mixed(const fbl_plan *p, const float *x, const float *g, 
     return hipGetLastError();
 }
 
-int step_blocks(const fbl_plan *p)
+
+static int blocks_for(int64_t d)
 {
-    const int64_t d = (int64_t)p->geo.nx * p->geo.ny * p->geo.nz;
     const int64_t need = (d + 255) / 256;
     return (int)(need < kStepBlocks ? need : kStepBlocks);
 }
 
+int step_blocks(const fbl_plan *p) { return blocks_for((int64_t)p->geo.nx * p->geo.ny * p->geo.nz); }
+
 template <typename TV, bool SR>
-static hipError_t launch_step_t(const fbl_plan *p, const void *x, const float *g, double alpha, double amu,
-                                double lo, double hi, uint64_t key, void *xbar, int blocks, hipStream_t st)
+static hipError_t launch_step_t(int64_t d, const void *x, const float *g, double alpha, double amu, double lo,
+                                double hi, uint64_t key, void *xbar, double *partials, int blocks, hipStream_t st)
 {
-    const int64_t d = (int64_t)p->geo.nx * p->geo.ny * p->geo.nz;
     hipLaunchKernelGGL((step_kernel<TV, SR>), dim3(blocks), dim3(256), 0, st, (const TV *)x, g, alpha, amu, lo, hi,
-                       key, (TV *)xbar, d, p->d_partials);
+                       key, (TV *)xbar, d, partials);
     return hipGetLastError();
 }
 
 template <bool SR>
-static hipError_t launch_step_r(const fbl_plan *p, const void *x, const float *g, double alpha, double amu,
-                                double lo, double hi, uint64_t key, void *xbar, int blocks, hipStream_t st)
+static hipError_t launch_step_r(int32_t vol_dtype, int64_t d, const void *x, const float *g, double alpha,
+                                double amu, double lo, double hi, uint64_t key, void *xbar, double *partials,
+                                int blocks, hipStream_t st)
 {
-    switch (p->vol_dtype) {
-    case FBL_F32: return launch_step_t<float, SR>(p, x, g, alpha, amu, lo, hi, key, xbar, blocks, st);
-    case FBL_BF16: return launch_step_t<__hip_bfloat16, SR>(p, x, g, alpha, amu, lo, hi, key, xbar, blocks, st);
-    default: return launch_step_t<__half, SR>(p, x, g, alpha, amu, lo, hi, key, xbar, blocks, st);
+    switch (vol_dtype) {
+    case FBL_F32: return launch_step_t<float, SR>(d, x, g, alpha, amu, lo, hi, key, xbar, partials, blocks, st);
+    case FBL_BF16:
+        return launch_step_t<__hip_bfloat16, SR>(d, x, g, alpha, amu, lo, hi, key, xbar, partials, blocks, st);
+    default: return launch_step_t<__half, SR>(d, x, g, alpha, amu, lo, hi, key, xbar, partials, blocks, st);
     }
 }
 
@@ -188,11 +193,72 @@ hipError_t launch_step(const fbl_plan *p, const void *x, const float *g, double 
                        double hi, bool stochastic, uint64_t key, void *xbar, int64_t *n_partials_used,
                        hipStream_t st)
 {
-    const int blocks = step_blocks(p);
+    const int64_t d = (int64_t)p->geo.nx * p->geo.ny * p->geo.nz;
+    const int blocks = blocks_for(d);
     *n_partials_used = blocks;
     const double amu = alpha * mu;
-    return stochastic ? launch_step_r<true>(p, x, g, alpha, amu, lo, hi, key, xbar, blocks, st)
-                      : launch_step_r<false>(p, x, g, alpha, amu, lo, hi, key, xbar, blocks, st);
+    return stochastic
+               ? launch_step_r<true>(p->vol_dtype, d, x, g, alpha, amu, lo, hi, key, xbar, p->d_partials, blocks, st)
+               : launch_step_r<false>(p->vol_dtype, d, x, g, alpha, amu, lo, hi, key, xbar, p->d_partials, blocks,
+                                      st);
+}
+
+// ---- the allocation-free prox trial ---------------------------------------------------
+//
+// Its FP64 block partials live in a file-scope device array instead of a plan: at most
+// kStepBlocks blocks each write three sums, whatever the volume size.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for the symbol):
+// the device address is taken once per device with hipGetSymbolAddress and kept.
+constexpr int kScratchDoubles = 3 * kStepBlocks;   // 48 KiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static double *g_scratch_ptr[kMaxDevices];
+
+static hipError_t scratch_of_current_device(double **out, int *dev_out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    *dev_out = dev;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace fbl
+
+extern "C" int fb_lisa_step_noalloc(int64_t n_voxels, int32_t vol_dtype, const void *x, const float *g, double alpha,
+                                    double mu, double lo, double hi, void *xbar, double *red_dev, void *stream)
+{
+    using namespace fbl;
+    if (vol_dtype != FBL_F32 && vol_dtype != FBL_BF16 && vol_dtype != FBL_F16)
+        return set_error(FBL_E_DTYPE, "vol_dtype %d is not FBL_F32, FBL_BF16 or FBL_F16", (int)vol_dtype);
+    if (n_voxels < 1 || n_voxels >= ((int64_t)1 << 31))
+        return set_error(FBL_E_RANGE, "n_voxels = %lld outside [1, 2^31): the allocation-free prox trial holds "
+                                      "at most %d blocks' partial sums for volumes below 2^31 voxels",
+                         (long long)n_voxels, kStepBlocks);
+    const int rc = check_step_buffers(x, g, alpha, mu, lo, hi, xbar, red_dev);
+    if (rc != FBL_OK) return rc;
+    double *partials = nullptr;
+    int dev = -1;
+    hipError_t e = scratch_of_current_device(&partials, &dev);
+    if (e != hipSuccess)
+        return set_error(FBL_E_HIP, "device scratch of the allocation-free prox trial (device %d): %s", dev,
+                         hipGetErrorString(e));
+    const int blocks = blocks_for(n_voxels);
+    hipStream_t st = (hipStream_t)stream;
+    e = launch_step_r<false>(vol_dtype, n_voxels, x, g, alpha, alpha * mu, lo, hi, 0, xbar, partials, blocks, st);
+    if (e != hipSuccess) return set_error(FBL_E_HIP, "step launch: %s", hipGetErrorString(e));
+    e = launch_finalize_sum(partials, blocks, 3, 1.0, red_dev, st);
+    if (e != hipSuccess) return set_error(FBL_E_HIP, "step reduction launch: %s", hipGetErrorString(e));
+    return clear_error();
+}
