@@ -1,16 +1,23 @@
 #!/usr/bin/env python
 """Benchmark of the FB-LISA hot path on one MI355X.
 
-A step is one FB-LISA iteration (Algorithm 1, Steps 2a-2d) of the 256^3 workload:
-the forward projection of a 20-view mini-batch with residual and FP64 objective, the
-backprojection (gradient), and the line search's prox trials, each followed by a
-forward projection of the trial point and one read-back of three FP64 scalars.
-Inputs (phantom, noisy data, view draws) are synthetic, seeded and already resident
-in device memory when the timed region starts.
+The default workload is the 1024^3 one: a 1024^3 FP32 ellipsoid phantom (30 ellipsoids),
+1440 views of a 1536x1536 detector, 40-view mini-batches, 10 epochs, nonnegativity prox,
+1% Gaussian noise on exact line integrals.  A step is one FB-LISA iteration (Algorithm 1,
+Steps 2a-2d) of the plain FP32 method: the forward projection of the mini-batch with
+residual and FP64 objective, the backprojection (gradient), and the line search's prox
+trials, each followed by a forward projection of the trial point and one read-back of
+three FP64 scalars.  Inputs (phantom, noisy data, view draws) are synthetic, seeded and
+already resident in device memory when the timed region starts.
 
 value = projector updates per second over the timed steps (GUPS): every forward or
 backprojection call over B views counts d*B voxel-view updates (d voxels); the time
 includes the step kernels, the reductions and the per-trial host synchronisation.
+
+After the timed steps the same workload runs the time-to-RMSE comparison: the plain FP32
+method against the learned initial step with the projector reading a BF16 copy of the
+volume and FP16 data, each given the plain run's wall time.  A secondary block repeats
+throughput and the comparison at 256^3 (three view orders).
 
 Printed: one JSON line on stdout (diagnostics go to stderr).
 """
@@ -32,13 +39,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FP+BP GUPS & %HBM roofline; FB-LISA time-to-RMSE, learned+BF16 vs plain"
 HBM_PEAK_GBS = 8000.0
+DEVICE_DATA = ("c3", "c5")   # workloads whose exact line integrals are computed on the GPU
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = {"fp_kernel": "forward.hip", "bp_kernel": "backproject.hip"}
+KERNEL_SOURCES = {"fp_kernel": "forward.hip", "bp_kernel": "backproject.hip", "step_kernel": "step.hip"}
 
 
 def kernel_source_hash(kernel: str) -> str:
@@ -55,9 +63,10 @@ def kernel_source_hash(kernel: str) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, cfg: str):
-    """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source (else None)."""
+def profile_value(kernel: str, cfg: str, field: str = "hbm_bytes_per_launch"):
+    """A figure of a kernel from the committed rocprofv3 counter summary
+    profiles/<kernel>_<cfg>_pmc.json, if it was taken on the current kernel source (else
+    None): HBM bytes per launch, VALU issue fraction or L2 hit rate."""
     path = os.path.join(ROOT, "profiles", "%s_%s_pmc.json" % (kernel, cfg))
     if not os.path.exists(path):
         return None
@@ -65,11 +74,91 @@ def measured_traffic(kernel: str, cfg: str):
         rec = json.load(fh)
     if rec.get("kernel_source_hash") != kernel_source_hash(kernel):
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get(field)
 
 
-def cpu_baseline(g, b32, perms, B, alpha0, beta, lo, hi, min_seconds=12.0, max_iters=4):
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload: FB-LISA
+def measured_traffic(kernel: str, cfg: str):
+    """HBM bytes per launch of a kernel from its committed counter summary (or None)."""
+    return profile_value(kernel, cfg, "hbm_bytes_per_launch")
+
+
+def host_info():
+    """CPU model name (as lscpu reports it, from /proc/cpuinfo) and the logical CPUs."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count()}
+
+
+def make_workload(syn, name):
+    """The seeded synthetic workload of a configuration: (geometry, config, seed, FP64
+    phantom on the host, FP32 data [n_views][nv][nu] on the GPU).  The data are the exact
+    line integrals through the phantom's ellipsoids plus 1% Gaussian noise; for the 512^3
+    and 1024^3 workloads they are computed on the GPU and the phantom is voxelised at one
+    sample per voxel (the host loops would take a quarter of an hour)."""
+    import torch
+    cfg = syn.CONFIGS[name]
+    g = syn.config_geometry(name)
+    seed = 1000 * int(name[1:])
+    if name in DEVICE_DATA:
+        ells, xt = syn.phantom(g, cfg["k"], seed=seed, hi=cfg["hi"], sub=1)
+        b = torch.empty((g.n_views, g.nv, g.nu), dtype=torch.float32, device="cuda")
+        chunk = 60
+        for v0 in range(0, g.n_views, chunk):   # FP64 line integrals a few views at a time
+            vv = np.arange(v0, min(g.n_views, v0 + chunk))
+            b[v0:v0 + len(vv)] = syn.ellipsoid_line_integrals_torch(g, ells, vv, device="cuda").float()
+        syn.add_noise_torch(b, 0.01, seed=seed + 1)
+    else:
+        ells, xt = syn.phantom(g, cfg["k"], seed=seed, hi=cfg["hi"])
+        clean = syn.ellipsoid_line_integrals(g, ells, np.arange(g.n_views))
+        b = torch.from_numpy(syn.add_noise(clean, 0.01, seed=seed + 1).astype(np.float32)).cuda()
+        del clean
+    torch.cuda.synchronize()
+    return g, cfg, seed, xt, b
+
+
+def cpu_baseline_rays(g, xt, views, min_seconds=10.0, max_rays=1 << 24, seed=77):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload: its ray-subset
+    forward projector (every slice of each ray, the same per-ray work as a full view)
+    on seeded random rays of the mini-batch, in rounds of doubling size until about
+    min_seconds of host time.  A full view of n_p rays counts d voxel-view updates, so a
+    ray counts d / n_p."""
+    import oracle
+    x64 = np.ascontiguousarray(np.asarray(xt, dtype=np.float64))
+    rng = np.random.default_rng(seed)
+    n, done, dt = 256, 0, 0.0
+    while dt < min_seconds and done < max_rays:
+        rays = np.stack([np.asarray(views)[rng.integers(0, len(views), n)], rng.integers(0, g.nv, n),
+                         rng.integers(0, g.nu, n)], 1)
+        t0 = time.perf_counter()
+        oracle.forward_rays(g, x64, rays)
+        dt += time.perf_counter() - t0
+        done += n
+        n *= 2
+    per_ray = dt / done
+    hi = host_info()
+    return {
+        "value": (g.d / g.n_p) / per_ray / 1e9,
+        "unit": "GUPS",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": "%d seeded random rays of the %d-view mini-batch through the oracle's FP64 ray-subset forward "
+                  "projector (%d slices per ray) in %.1f s: %.3g ms per ray; a view's %d rays count %d voxel-view "
+                  "updates" % (done, len(views), g.nx, dt, per_ray * 1e3, g.n_p, g.d),
+        "seconds_per_ray": per_ray,
+        "cpu_model": hi["cpu_model"],
+        "logical_cpus": hi["logical_cpus"],
+    }
+
+
+def cpu_baseline_iterations(g, b32, perms, B, alpha0, beta, lo, hi, min_seconds=12.0, max_iters=4):
+    """The FP64 oracle, as it stands, on a bounded sample of a small workload: FB-LISA
     iterations from x = 0 on the run's first mini-batches, until about min_seconds of host
     time have passed (at most max_iters iterations)."""
     import oracle
@@ -144,124 +233,258 @@ def warm_clock(fbl, plan, x, views, r, g, seconds=None):
         torch.cuda.synchronize()
 
 
-def time_to_rmse(fbl, g, cfg, b32, xt, perms, proposer, variants=("bf16", "bf16_nearest", "f16", "f32")):
-    """Wall time to the reconstruction error of the plain FP32 run: the plain FP32 run sets
-    RMSE* (its error after the configured epochs) and is timed to its first iterate at or
-    below RMSE*; the learned-step runs are timed to the same target.  A learned run that has
-    not reached it after the configured epochs goes on, in the last epoch's setting, up to
-    len(perms) iterations (perms rows beyond the configured ones).  Device-synchronised
-    host clock; RMSE evaluations excluded."""
-    import torch
-    xt_dev = torch.from_numpy(xt.astype(np.float32)).cuda()
 
-    class Reached(Exception):
+def summarize(values):
+    v = np.asarray(values, dtype=np.float64)
+    return {"median": round(float(np.median(v)), 2), "min": round(float(v.min()), 2),
+            "max": round(float(v.max()), 2), "p10": round(float(np.percentile(v, 10)), 2),
+            "p90": round(float(np.percentile(v, 90)), 2), "n": int(v.size)}
+
+
+def rmse_race(fbl, g, cfg, b_f32, xt_dev, perms, runs, warm_s=None):
+    """Time to the reconstruction error of the plain FP32 run, at equal wall-clock budgets.
+
+    The plain FP32 method runs its configured epochs; its elapsed time T is every run's
+    budget, its final RMSE is the target RMSE*, its smallest RMSE the second target.  Each
+    other run (learned initial step, with the projector reading a 16-bit copy of the
+    volume and 16-bit data, or FP32) runs for the same wall time T: its configured epochs,
+    then, if time remains, more iterations in the last epoch's setting.  Reported per run:
+    the time and iterations to RMSE* and to the plain run's minimum, RMSE and RE at T/2
+    and T, forward calls per iteration and the backtrack histogram.  Device-synchronised
+    host clock; the RMSE evaluations are excluded by timestamps.
+
+    runs: list of (name, dict(vol_dtype, mixed, sr_seed, proj16, learned proposer or None)).
+    """
+    import torch
+    nrm_t = float(torch.linalg.vector_norm(xt_dev.double()))
+    sqd = math.sqrt(g.d)
+
+    class Budget(Exception):
         pass
 
-    def go(b_dev, vol_dtype, alpha_init, target, sr_seed=None):
-        # the constant-batch C keeps N_t = N_0 for the configured epochs, so buffers for
-        # one batch suffice (n_max)
-        run = fbl.FBLisa(g, b_dev, n0=cfg["batch"], epochs=cfg["epochs"], lo=cfg["lo"], hi=cfg["hi"],
-                         vol_dtype=vol_dtype, sr_seed=sr_seed, n_max=cfg["batch"])
+    def go(name, b_dev, vol_dtype, alpha_init, budget, mixed=False, sr_seed=None):
+        B = cfg["batch"]
+        run = fbl.FBLisa(g, b_dev, n0=B, epochs=cfg["epochs"], lo=cfg["lo"], hi=cfg["hi"], vol_dtype=vol_dtype,
+                         sr_seed=sr_seed, n_max=B, mixed=mixed)
         st = {"excluded": 0.0, "t": [], "rmse": []}
 
         def cb(r, it):
             t_in = time.perf_counter()
-            st["t"].append(t_in - st["t0"] - st["excluded"])   # the iterate is complete (read back)
+            el = t_in - st["t0"] - st["excluded"]            # the iterate is complete (read back)
+            st["t"].append(el)
             e = float(torch.sqrt(torch.mean((r.x.float() - xt_dev) ** 2)))
             st["rmse"].append(e)
-            if len(st["rmse"]) % 50 == 0:   # progress of long runs (outside the timed intervals)
-                log("  %s: iteration %d, rmse %.4e" % (vol_dtype, len(st["rmse"]), e))
+            if len(st["rmse"]) % 60 == 0:                    # progress of long runs
+                log("  %s: iteration %d, %.1f s, rmse %.4e" % (name, len(st["rmse"]), el, e))
             st["excluded"] += time.perf_counter() - t_in
-            if target is not None and e <= target:
-                raise Reached()
+            if budget is not None and el >= budget:
+                raise Budget()
 
-        B0 = cfg["batch"]
-        warm_clock(fbl, run.plan, run.x, perms[0][:B0], run.r[:B0], run.g)
+        warm_clock(fbl, run.plan, run.x16, perms[0][:B], run.r[:B], run.g, warm_s)
         torch.cuda.synchronize()
         st["t0"] = time.perf_counter()
         try:
             run.run(perms, alpha_init=alpha_init, callback=cb)
-            if target is not None:
-                n_cfg = len(run.history)
-                for k in range(n_cfg, len(perms)):
-                    cb(run, run.iterate(perms[k][:cfg["batch"]], alpha_init, epoch=run.epochs))
-        except Reached:
+            if budget is not None:
+                for k in range(len(run.history), len(perms)):
+                    cb(run, run.iterate(perms[k][:B], alpha_init, epoch=run.epochs))
+        except Budget:
             pass
-        return run.history, st
+        hist = run.history
+        run = None
+        torch.cuda.empty_cache()
+        return hist, st
 
-    b_f32 = b32 if torch.is_tensor(b32) else torch.from_numpy(b32).cuda()
-    hist_p, st_p = go(b_f32, "f32", None, None)
+    hist_p, st_p = go("plain f32", b_f32, "f32", None, None)
+    T = st_p["t"][-1]
     target = st_p["rmse"][-1]
-    k_p = next(i for i, e in enumerate(st_p["rmse"]) if e <= target) + 1
-    b16 = b_f32.half()
-    hist_l, st_l = go(b16, "bf16", proposer, target, sr_seed=2024)
-    k_l = len(hist_l)
-    reached = st_l["rmse"][-1] <= target
-    if "bf16_nearest" in variants:
-        hist_n, st_n = go(b16, "bf16", proposer, target)
-    if "f16" in variants:
-        hist_h, st_h = go(b16, "f16", proposer, target, sr_seed=2024)
-    if "f32" in variants:
-        hist_f, st_f = go(b_f32, "f32", proposer, target)
+    best = min(st_p["rmse"])
 
-    def summary(hist, st, k):
-        h = hist[:k]
-        return {"seconds": round(st["t"][k - 1], 4), "iterations": k, "rmse": st["rmse"][k - 1],
-                "fp_calls_per_iter": round(float(np.mean([2 + it.backtracks for it in h])), 3),
-                "backtracks_per_iter": round(float(np.mean([it.backtracks for it in h])), 3)}
+    def first(st, thr):
+        i = next((i for i, e in enumerate(st["rmse"]) if e <= thr), None)
+        return None if i is None else (round(st["t"][i], 4), i + 1)
 
-    rec = {
-        "rmse_target": target,
-        "plain_f32": summary(hist_p, st_p, k_p),
-        "learned_bf16": dict(summary(hist_l, st_l, k_l), reached=reached,
-                             storage="BF16 volume (stochastic rounding), FP16 data"),
-    }
-    if "bf16_nearest" in variants:
-        rec["learned_bf16_nearest"] = dict(summary(hist_n, st_n, len(hist_n)), reached=st_n["rmse"][-1] <= target)
-    if "f16" in variants:
-        rec["learned_f16"] = dict(summary(hist_h, st_h, len(hist_h)), reached=st_h["rmse"][-1] <= target,
-                                  storage="FP16 volume (stochastic rounding), FP16 data")
-    if "f32" in variants:
-        rec["learned_f32"] = dict(summary(hist_f, st_f, len(hist_f)), reached=st_f["rmse"][-1] <= target)
-    rec["speedup"] = round(st_p["t"][k_p - 1] / st_l["t"][k_l - 1], 3) if reached else None
+    def at_time(st, t):
+        i = max([j for j, tt in enumerate(st["t"]) if tt <= t], default=None)
+        if i is None:
+            return None
+        return {"rmse": st["rmse"][i], "re": st["rmse"][i] * sqd / nrm_t, "iterations": i + 1}
+
+    def summary(hist, st):
+        bt = [it.backtracks for it in hist]
+        hist_bt = {}
+        for b_ in bt:
+            hist_bt[str(b_)] = hist_bt.get(str(b_), 0) + 1
+        tt = first(st, target)
+        tm = first(st, best)
+        return {"to_rmse_target": None if tt is None else {"seconds": tt[0], "iterations": tt[1]},
+                "to_plain_min_rmse": None if tm is None else {"seconds": tm[0], "iterations": tm[1]},
+                "at_half_budget": at_time(st, 0.5 * T), "at_budget": at_time(st, T),
+                "iterations": len(hist), "seconds": round(st["t"][-1], 4),
+                "fp_calls_per_iter": round(float(np.mean([2 + b_ for b_ in bt])), 3),
+                "backtracks_per_iter": round(float(np.mean(bt)), 3),
+                "backtrack_histogram": dict(sorted(hist_bt.items(), key=lambda kv: int(kv[0])))}
+
+    rec = {"rmse_target": target, "plain_min_rmse": best, "budget_s": round(T, 4),
+           "rule": "RMSE* is the plain FP32 run's RMSE after its configured epochs; every run gets that run's "
+                   "wall time T as its budget (configured epochs, then further iterations in the last epoch's "
+                   "setting while time remains); speedup = plain time to RMSE* / run's time to RMSE*",
+           "plain_f32": summary(hist_p, st_p)}
+    b16 = None
+    for name, spec in runs:
+        if spec.get("proj16") and b16 is None:
+            b16 = b_f32.half()
+        b_dev = b16 if spec.get("proj16") else b_f32
+        hist, st = go(name, b_dev, spec["vol_dtype"], spec.get("proposer"), T, mixed=spec.get("mixed", False),
+                      sr_seed=spec.get("sr_seed"))
+        sm = summary(hist, st)
+        sm["storage"] = spec["label"]
+        tp = rec["plain_f32"]["to_rmse_target"]["seconds"]
+        sm["speedup"] = (round(tp / sm["to_rmse_target"]["seconds"], 3)
+                         if sm["to_rmse_target"] is not None else None)
+        rec[name] = sm
+        log("  %s: speedup %s" % (name, sm["speedup"]))
+    del b16
+    torch.cuda.empty_cache()
     return rec
 
 
-def combined_run(fbl, syn, name: str = "c5"):
-    """The full combined run on one GPU: plain FP32 FB-LISA against the learned initial step
-    with BF16 volume storage (stochastic rounding) and FP16 data, timed to the plain run's
-    final RMSE; the same with FP16 volume storage for comparison.  The data are exact line integrals of the workload's ellipsoid phantom plus
-    1% Gaussian noise, computed on the GPU (the host loop would take a quarter of an hour at
-    1024^3); the phantom is voxelised at one sample per voxel."""
+LEARNED_RUNS = {
+    "learned_bf16": dict(vol_dtype="bf16", mixed=True, proj16=True,
+                         label="projector reads a BF16 copy of the FP32 iterate; FP16 data"),
+    "learned_bf16_sr": dict(vol_dtype="bf16", sr_seed=2024, proj16=True,
+                            label="BF16 iterate with stochastic rounding; FP16 data"),
+    "learned_f16": dict(vol_dtype="f16", mixed=True, proj16=True,
+                        label="projector reads an FP16 copy of the FP32 iterate; FP16 data"),
+    "learned_f32": dict(vol_dtype="f32", label="FP32 iterate and data"),
+}
+
+
+def timed_steps(fbl, g, cfg, b_dev, perms, steps, warmup, clock_warmup, per_iteration_timing):
+    """W warmup iterations, then exactly K timed iterations of the plain FP32 method, with
+    the projector (and prox-trial) launches bracketed by HIP events on the launch stream."""
     import torch
-    cfg = syn.CONFIGS[name]
-    g = syn.config_geometry(name)
     B = cfg["batch"]
-    seed = 1000 * int(name[1:])
-    t0 = time.perf_counter()
-    ells, xt = syn.phantom(g, cfg["k"], seed=seed, hi=cfg["hi"], sub=1)
-    t_ph = time.perf_counter() - t0
-    y = syn.ellipsoid_line_integrals_torch(g, ells, np.arange(g.n_views), device="cuda")
-    syn.add_noise_torch(y, 0.01, seed=seed + 1)
-    b32 = y.float()
-    del y
+    run = fbl.FBLisa(g, b_dev, n0=B, epochs=cfg["epochs"], alpha0=1e-3, beta=0.5, lo=cfg["lo"], hi=cfg["hi"],
+                     n_max=B)
+    warm_clock(fbl, run.plan, run.x, perms[0][:B], run.r[:B], run.g, clock_warmup)
+    for k in range(warmup):
+        run.iterate(perms[k][:B])
     torch.cuda.synchronize()
+    kernels = ("forward", "backproject", "step") if per_iteration_timing else ("forward", "backproject")
+    run.plan.timing(True, kernels=kernels)
+    n_hist = len(run.history)
+    per_it = {k: [] for k in kernels}
+    tot = {k: [0.0, 0] for k in kernels}
+    t0 = time.perf_counter()
+    for k in range(warmup, warmup + steps):
+        run.iterate(perms[k][:B])
+        if per_iteration_timing:   # the iteration has synchronised: its events are complete
+            kt = run.plan.timing_read()
+            for name in kernels:
+                ms, n = kt[name]
+                tot[name][0] += ms
+                tot[name][1] += n
+                if n:
+                    per_it[name].append(ms / n * 1e3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if not per_iteration_timing:
+        kt = run.plan.timing_read()
+        for name in kernels:
+            tot[name] = [kt[name][0], kt[name][1]]
+    run.plan.timing(False)
+    timed = run.history[n_hist:]
+    # a short supplementary pass with every launch bracketed gives the other kernels' means
+    k0 = warmup + steps
+    run.plan.timing(True)
+    for k in range(k0, k0 + 3):
+        run.iterate(perms[k][:B])
+    torch.cuda.synchronize()
+    ks = run.plan.timing_read()
+    run.plan.timing(False)
+    return run, timed, t1 - t0, tot, per_it, ks
+
+
+def phi_cone_fraction(fbl, g, views, B):
+    """Fraction of the voxels each view's rays touch (the cone of the view inside the
+    volume), from the backprojection of an all-ones residual: every tap weight is
+    nonnegative, so a voxel's value is nonzero exactly where some ray of the view reaches it
+    with nonzero weight.  Mean over the views."""
+    import torch
+    fr = []
+    with fbl.Plan(g, max_batch=1) as plan:
+        ones = torch.ones((1, g.nv, g.nu), dtype=torch.float32, device="cuda")
+        gg = torch.empty(g.vol_shape, dtype=torch.float32, device="cuda")
+        for v in views[:B]:
+            fbl.fb_lisa_backproject(plan, ones, [int(v)], grad_scale=1.0, g=gg)
+            fr.append(float((gg != 0).sum()) / g.d)
+        del gg, ones
     torch.cuda.empty_cache()
-    t_data = time.perf_counter() - t0
-    log("combined run %s: phantom %.1f s, data %.1f s" % (name, t_ph, t_data))
-    model, n_samples, curve = train_step_proposer(fbl, syn)
-    n_it = cfg["epochs"] * math.ceil(g.n_views / B)
-    perms = syn.view_permutations(g.n_views, 2 * n_it, seed=seed + 2)
-    # BF16 (the run's storage) and, for comparison, FP16 storage with the same proposer
-    tt = time_to_rmse(fbl, g, cfg, b32, xt, perms, fbl.LearnedStep(model), variants=("bf16", "f16"))
-    return {"mode": "combined run",
-            "workload": "%s: %d^3 ellipsoid phantom (%d ellipsoids, voxelised at 1 sample per voxel), %d views, "
-                        "%dx%d detector, mini-batch %d, %d epochs, prox [%g, %g], 1%% Gaussian noise on exact line "
-                        "integrals" % (name, g.nx, cfg["k"], g.n_views, g.nu, g.nv, B, cfg["epochs"], cfg["lo"],
-                                       cfg["hi"]),
-            "setup_s": round(t_data, 1),
-            "proposer": "5-64-64-1 perceptron trained on %d iterations of 200 seeded 64^3 runs" % n_samples,
-            "time_to_rmse": tt}
+    return float(np.mean(fr))
+
+
+def projector_block(fbl, syn, name, g, cfg, b_dev, perms, steps, warmup, clock_warmup, per_iteration_timing):
+    """Throughput of the timed steps and the projector kernels against their rooflines."""
+    B = cfg["batch"]
+    run, timed, wall, tot, per_it, ks = timed_steps(fbl, g, cfg, b_dev, perms, steps, warmup, clock_warmup,
+                                                    per_iteration_timing)
+    n_fp, n_bp = tot["forward"][1], tot["backproject"][1]
+    gups = (n_fp + n_bp) * g.d * B / wall / 1e9
+    t_fp = tot["forward"][0] / n_fp * 1e-3
+    t_bp = tot["backproject"][0] / n_bp * 1e-3
+    kernel_us = {k: round(ms / n * 1e3, 2) for k, (ms, n) in ks.items() if n}
+    kernel_us.update({k: round(tot[k][0] / tot[k][1] * 1e3, 2) for k in tot if tot[k][1]})
+    t_st = (tot["step"][0] / tot["step"][1] * 1e-3) if "step" in tot and tot["step"][1] else \
+        ks["step"][0] / ks["step"][1] * 1e-3
+    bytes_view = B * (g.d * 4 + 4 * g.n_p)
+    bytes_min = g.d * 4 + B * g.n_p * (4 + 4)
+    share = {"fp_kernel": tot["forward"][0], "bp_kernel": tot["backproject"][0]}
+    dominant = max(share, key=share.get)
+    t_dom = t_fp if dominant == "fp_kernel" else t_bp
+    other = "bp_kernel" if dominant == "fp_kernel" else "fp_kernel"
+    t_other = t_bp if dominant == "fp_kernel" else t_fp
+    achieved = bytes_view / t_dom / 1e9
+    out = {
+        "gups": gups, "wall": wall, "B": B,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dominant, name),
+            "kernel": dominant,
+            "bytes_per_launch": bytes_view,
+            "compulsory_bytes_per_launch": bytes_min,
+            "compulsory_frac": round(bytes_min / t_dom / 1e9 / HBM_PEAK_GBS, 4),
+            "valu_busy": profile_value(dominant, name, "valu_busy"),
+            "l2_hit_rate": profile_value(dominant, name, "l2_hit_rate"),
+            "share_of_timed_region": round(share[dominant] / (wall * 1e3), 4),
+        },
+        "roofline_other": {
+            "kernel": other,
+            "achieved": round(bytes_view / t_other / 1e9, 1),
+            "frac": round(bytes_view / t_other / 1e9 / HBM_PEAK_GBS, 4),
+            "compulsory_frac": round(bytes_min / t_other / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(other, name),
+            "valu_busy": profile_value(other, name, "valu_busy"),
+            "l2_hit_rate": profile_value(other, name, "l2_hit_rate"),
+            "share_of_timed_region": round(share[other] / (wall * 1e3), 4),
+        },
+        "pair_frac": round(2 * bytes_view / (t_fp + t_bp) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernel_us": kernel_us,
+        "step_hbm": {"bytes_per_launch": 12 * g.d, "achieved": round(12 * g.d / t_st / 1e9, 1),
+                     "frac": round(12 * g.d / t_st / 1e9 / HBM_PEAK_GBS, 4)},
+        "gups_per_op": {"forward": round(g.d * B / t_fp / 1e9, 2), "backproject": round(g.d * B / t_bp / 1e9, 2)},
+        "gsamples_per_s": {"forward": round(B * g.n_p * g.nx / t_fp / 1e9, 2),
+                           "backproject": round(B * g.n_p * g.nx / t_bp / 1e9, 2)},
+        "calls": {"forward": n_fp, "backproject": n_bp, "step": sum(len(it.trials) for it in timed)},
+        "mean_backtracks": float(np.mean([it.backtracks for it in timed])),
+    }
+    if per_iteration_timing:
+        out["per_launch_us"] = {k: summarize(v) for k, v in per_it.items() if v}
+    return out, run
 
 
 def paper_shaped_run(fbl, syn, seconds: float, views: int = 72, n: int = 560, n0: int = 8, seed: int = 5600):
@@ -386,6 +609,7 @@ def kernel_scaling(fbl, syn, names, reps=5, storage="f32"):
     return {"mode": "kernel scaling", storage: out}
 
 
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -394,10 +618,18 @@ def main(argv=None):
     ap.add_argument("--clock-warmup", type=float, default=CLOCK_WARMUP_S, metavar="SECONDS",
                     help="projector launches on the initial iterate before the warmup steps, so the timed "
                          "region runs at the GPU's working clock (no state of the run changes)")
-    ap.add_argument("--config", default="c2", help="workload (c1..c4); the default is the metric's")
+    ap.add_argument("--config", default="c5",
+                    help="workload (c1..c5); the default, c5 (1024^3, 1440 views, 1536^2, batch 40), is the one "
+                         "the metric's time-to-RMSE comparison is defined on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-rmse", action="store_true",
                     help="skip the time-to-RMSE comparison (learned step + BF16 storage against plain FP32)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the secondary 256^3 block (throughput and a three-order time-to-RMSE comparison)")
+    ap.add_argument("--no-cone-fraction", action="store_true",
+                    help="skip the cone fraction (one single-view backprojection per view of the batch)")
+    ap.add_argument("--variants", default="learned_bf16",
+                    help="learned runs of the main comparison, comma-separated from %s" % ",".join(LEARNED_RUNS))
     ap.add_argument("--probe", action="store_true",
                     help="counter-collection run: 3 forward, 1 backprojection, 1 step call of the workload, then "
                          "a plain 512 MiB device copy whose FETCH_SIZE/WRITE_SIZE calibrate the counters")
@@ -406,9 +638,6 @@ def main(argv=None):
                          "72-view synthetic stand-in, for this many seconds")
     ap.add_argument("--kernel-storage", default="f32", choices=("f32", "bf16", "f16"),
                     help="volume storage type for --kernels")
-    ap.add_argument("--combined-run", default="", metavar="CONFIG",
-                    help="instead of the benchmark: the full combined run (plain FP32 against learned step + BF16 "
-                         "storage, time to the plain run's RMSE) at this workload, e.g. c5")
     ap.add_argument("--kernels", default="", metavar="CONFIGS",
                     help="instead of the benchmark: time the projector and step kernels alone at these workloads "
                          "(comma-separated, e.g. c3,c5)")
@@ -430,103 +659,53 @@ def main(argv=None):
         print(json.dumps(kernel_scaling(fbl, syn, [c for c in args.kernels.split(",") if c],
                                         storage=args.kernel_storage)), flush=True)
         return 0
-    if args.combined_run:
-        print(json.dumps(combined_run(fbl, syn, args.combined_run)), flush=True)
-        return 0
     if args.paper_run > 0:
         print(json.dumps(paper_shaped_run(fbl, syn, args.paper_run)), flush=True)
         return 0
-    cfg = syn.CONFIGS[args.config]
-    g = syn.config_geometry(args.config)
-    B = cfg["batch"]
-    seed = 1000 * int(args.config[1:])
-    t_setup = time.perf_counter()
-    ells, xt = syn.phantom(g, cfg["k"], seed=seed, hi=cfg["hi"])
-    clean = syn.ellipsoid_line_integrals(g, ells, np.arange(g.n_views))
-    b32 = syn.add_noise(clean, 0.01, seed=seed + 1).astype(np.float32)
-    del clean
-    perms = syn.view_permutations(g.n_views, args.warmup + args.steps + 3, seed=seed + 2)
-    log("setup (phantom, exact line integrals, noise): %.1f s" % (time.perf_counter() - t_setup))
-
-    b_dev = torch.from_numpy(b32).cuda()
-    alpha0, beta = 1e-3, 0.5
+    name = args.config
     if args.probe:
+        # values do not change the kernels' work: a seeded random volume and zero data
+        cfg = syn.CONFIGS[name]
+        g = syn.config_geometry(name)
+        B = cfg["batch"]
         plan = fbl.Plan(g, max_batch=B)
-        x = torch.from_numpy(xt.astype(np.float32)).cuda()
-        views = perms[0][:B]
+        x = torch.from_numpy(syn.random_volume(g, seed=5)).cuda()
+        b_dev = torch.zeros((g.n_views, g.nv, g.nu), dtype=torch.float32, device="cuda")
+        views = syn.view_permutations(g.n_views, 1, seed=1000 * int(name[1:]) + 2)[0][:B]
         loss = torch.zeros(1, dtype=torch.float64, device="cuda")
         for _ in range(3):
             r = fbl.fb_lisa_forward(plan, x, views, b_dev, loss=loss)
         gr = fbl.fb_lisa_backproject(plan, r, views)
-        fbl.fb_lisa_step(plan, x, gr, alpha0, 0.0, cfg["lo"], cfg["hi"])
+        fbl.fb_lisa_step(plan, x, gr, 1e-3, 0.0, cfg["lo"], cfg["hi"])
         torch.cuda.synchronize()
         src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"probe": args.config, "copy_bytes": src.numel() * 4,
+        print(json.dumps({"probe": name, "copy_bytes": src.numel() * 4,
                           "forward_bytes_model": B * (g.d * 4 + 4 * g.n_p)}), flush=True)
         return 0
-    run = fbl.FBLisa(g, b_dev, n0=B, epochs=cfg["epochs"], alpha0=alpha0, beta=beta, lo=cfg["lo"], hi=cfg["hi"])
-    warm_clock(fbl, run.plan, run.x, perms[0][:B], run.r[:B], run.g, args.clock_warmup)
-    for k in range(args.warmup):
-        run.iterate(perms[k][:B])
-    torch.cuda.synchronize()
-    # HIP events (on the launch stream) around the projector kernels' launches only: each
-    # bracketed launch adds two event records to the stream, so timing every launch of an
-    # iteration would slow the timed region itself
-    run.plan.timing(True, kernels=("forward", "backproject"))
-    n_hist = len(run.history)
-    t0 = time.perf_counter()
-    for k in range(args.warmup, args.warmup + args.steps):
-        run.iterate(perms[k][:B])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kt = run.plan.timing_read()
-    run.plan.timing(False)
-    timed = run.history[n_hist:]
-    # a short supplementary pass with every launch bracketed gives the other kernels' means
-    k0 = args.warmup + args.steps
-    run.plan.timing(True)
-    for k in range(k0, k0 + 3):
-        run.iterate(perms[k][:B])
-    torch.cuda.synchronize()
-    ks = run.plan.timing_read()
-    run.plan.timing(False)
-    n_fp = kt["forward"][1]
-    n_bp = kt["backproject"][1]
-    updates = (n_fp + n_bp) * g.d * B
-    wall = t1 - t0
-    gups = updates / wall / 1e9
-    kernel_us = {k: round(ms / n * 1e3, 2) for k, (ms, n) in ks.items() if n}
-    kernel_us.update({k: round(kt[k][0] / kt[k][1] * 1e3, 2) for k in ("forward", "backproject")})
-    t_fp = kt["forward"][0] / n_fp * 1e-3            # fp_kernel alone (timed region)
-    t_bp = kt["backproject"][0] / n_bp * 1e-3        # bp_kernel alone (timed region)
-    t_fin = ks["finalize"][0] / max(1, ks["finalize"][1]) * 1e-3
-    n_fp_s = max(1, ks["forward"][1])
-    t_fp_call = t_fp + ks["transpose"][0] / n_fp_s * 1e-3 + t_fin   # whole forward call
-    t_bp_call = t_bp + ks["prescale"][0] / max(1, ks["backproject"][1]) * 1e-3
-    t_st = ks["step"][0] / ks["step"][1] * 1e-3                # step_kernel alone
 
-    # roofline of the dominant kernel (the projector kernel with the larger share of the
-    # timed region): the per-view block model, each view reads the volume once and writes
-    # (forward) or reads (backprojection) its n_p FP32 values
-    bytes_view = B * (g.d * 4 + 4 * g.n_p)
-    share = {"fp_kernel": kt["forward"][0], "bp_kernel": kt["backproject"][0]}
-    dominant = max(share, key=share.get)
-    t_dom = t_fp if dominant == "fp_kernel" else t_bp
-    achieved = bytes_view / t_dom / 1e9
-    other = "bp_kernel" if dominant == "fp_kernel" else "fp_kernel"
-    t_other = t_bp if dominant == "fp_kernel" else t_fp
+    t_setup = time.perf_counter()
+    g, cfg, seed, xt, b_dev = make_workload(syn, name)
+    B = cfg["batch"]
+    n_it = cfg["epochs"] * math.ceil(g.n_views / B)
+    perms = syn.view_permutations(g.n_views, max(args.warmup + args.steps + 3, 3 * n_it), seed=seed + 2)
+    log("setup of %s (phantom, exact line integrals, noise): %.1f s" % (name, time.perf_counter() - t_setup))
 
+    blk, run = projector_block(fbl, syn, name, g, cfg, b_dev, perms, args.steps, args.warmup, args.clock_warmup,
+                               per_iteration_timing=True)
+    del run
+    torch.cuda.empty_cache()
+    log("%s: %.1f GUPS, %.3f ms per step" % (name, blk["gups"], blk["wall"] / args.steps * 1e3))
     rec = {
         "metric": METRIC,
-        "value": round(gups, 3),
+        "value": round(blk["gups"], 3),
         "unit": "GUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "ms_per_step": round(blk["wall"] / args.steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -534,65 +713,73 @@ def main(argv=None):
         "data": "synthetic",
         "config": {
             "workload": "%s: %d^3 fp32 ellipsoid phantom (%d ellipsoids), %d views, %dx%d detector, "
-                        "mini-batch %d, prox [%g, %g], 1%% Gaussian noise on exact line integrals"
-                        % (args.config, g.nx, cfg["k"], g.n_views, g.nu, g.nv, B, cfg["lo"], cfg["hi"]),
+                        "mini-batch %d, %d epochs, prox [%g, %g], 1%% Gaussian noise on exact line integrals"
+                        % (name, g.nx, cfg["k"], g.n_views, g.nu, g.nv, B, cfg["epochs"], cfg["lo"], cfg["hi"]),
             "global_batch": B,
             "parallelism": "single GPU",
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(dominant, args.config),
-            "kernel": dominant,
-            "bytes_per_launch": bytes_view,
-            "share_of_timed_region": round(share[dominant] / (wall * 1e3), 4),
-        },
-        "roofline_other": {
-            "kernel": other,
-            "achieved": round(bytes_view / t_other / 1e9, 1),
-            "frac": round(bytes_view / t_other / 1e9 / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(other, args.config),
-            "share_of_timed_region": round(share[other] / (wall * 1e3), 4),
-        },
-        "kernel_us": kernel_us,
-        "step_hbm": {"bytes_per_launch": 12 * g.d, "achieved": round(12 * g.d / t_st / 1e9, 1),
-                     "frac": round(12 * g.d / t_st / 1e9 / HBM_PEAK_GBS, 4)},
-        "per_call_ms": {"forward": round(t_fp_call * 1e3, 4), "backproject": round(t_bp_call * 1e3, 4),
-                        "step": round(t_st * 1e3, 4)},
-        "gups_per_op": {"forward": round(g.d * B / t_fp / 1e9, 2), "backproject": round(g.d * B / t_bp / 1e9, 2)},
-        "calls": {"forward": n_fp, "backproject": n_bp, "step": sum(len(it.trials) for it in timed)},
-        "mean_backtracks": float(np.mean([it.backtracks for it in timed])),
     }
+    for k in ("roofline", "roofline_other", "pair_frac", "kernel_us", "per_launch_us", "step_hbm", "gups_per_op",
+              "gsamples_per_s", "calls", "mean_backtracks"):
+        if k in blk:
+            rec[k] = blk[k]
+    if not args.no_cone_fraction:
+        rec["roofline"]["cone_fraction"] = round(phi_cone_fraction(fbl, g, perms[0], B), 4)
+    xt_dev = torch.from_numpy(xt.astype(np.float32)).cuda()
+    model = None
     if not args.no_time_to_rmse:
         log("training the step proposer (200 plain runs of the 64^3 workload) ...")
         t_tr = time.perf_counter()
         model, n_samples, curve = train_step_proposer(fbl, syn)
         log("trained on %d samples in %.1f s (loss %.3e -> %.3e)" % (n_samples, time.perf_counter() - t_tr,
                                                                     curve[0], curve[-1]))
-        n_it = cfg["epochs"] * math.ceil(g.n_views / B)
-        # The iteration at which a run first reaches RMSE* moves by several iterations with
-        # small changes of the trajectory (the error curve is flat there), so the comparison
-        # is repeated over three view orders; each order's plain run sets its own RMSE*.
-        runs = []
-        for s_off in (2, 3, 4):
-            perms_run = syn.view_permutations(g.n_views, 2 * n_it, seed=seed + s_off)
-            runs.append(time_to_rmse(fbl, g, cfg, b32, xt, perms_run, fbl.LearnedStep(model)))
-            log("time to RMSE, view order %d: speedup %s" % (s_off, runs[-1]["speedup"]))
-        tt = runs[0]
+        prop = fbl.LearnedStep(model)
+        runs = [(v, dict(LEARNED_RUNS[v], proposer=prop)) for v in args.variants.split(",") if v]
+        log("time to RMSE at %s ..." % name)
+        tt = rmse_race(fbl, g, cfg, b_dev, xt_dev, perms, runs)
         tt["proposer"] = "5-64-64-1 perceptron trained on %d iterations of 200 seeded 64^3 runs" % n_samples
-        variants = ("learned_bf16", "learned_bf16_nearest", "learned_f16", "learned_f32")
-        per_order = {v: [round(r["plain_f32"]["seconds"] / r[v]["seconds"], 3) if r[v].get("reached", True) else None
-                         for r in runs] for v in variants}
-        tt["view_orders"] = {"seeds": [seed + s for s in (2, 3, 4)], "speedup": per_order,
-                             "median_speedup": {v: (float(np.median(x)) if all(y is not None for y in x) else None)
-                                                for v, x in per_order.items()}}
+        tt["view_order_seed"] = seed + 2
         rec["time_to_rmse"] = tt
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        rec["cpu_baseline"] = cpu_baseline(g, b32, perms, B, alpha0, beta, cfg["lo"], cfg["hi"])
+        if name in DEVICE_DATA:
+            rec["cpu_baseline"] = cpu_baseline_rays(g, xt, perms[0][:B])
+        else:
+            rec["cpu_baseline"] = cpu_baseline_iterations(g, b_dev.cpu().numpy(), perms, B, 1e-3, 0.5, cfg["lo"],
+                                                          cfg["hi"])
+            rec["cpu_baseline"].update(host_info())
+    del xt, xt_dev, b_dev
+    torch.cuda.empty_cache()
+    if not args.no_secondary and name != "c2":
+        log("secondary block: c2 ...")
+        g2, cfg2, seed2, xt2, b2 = make_workload(syn, "c2")
+        n_it2 = cfg2["epochs"] * math.ceil(g2.n_views / cfg2["batch"])
+        perms2 = syn.view_permutations(g2.n_views, max(args.warmup + args.steps + 3, 3 * n_it2), seed=seed2 + 2)
+        blk2, run2 = projector_block(fbl, syn, "c2", g2, cfg2, b2, perms2, args.steps, args.warmup,
+                                     args.clock_warmup, per_iteration_timing=False)
+        del run2
+        sec = {"workload": "c2: 256^3, 360 views, 384x384 detector, mini-batch 20, prox [0, 0.03]",
+               "value": round(blk2["gups"], 3), "ms_per_step": round(blk2["wall"] / args.steps * 1e3, 3)}
+        for k in ("roofline", "roofline_other", "pair_frac", "kernel_us", "step_hbm", "calls", "mean_backtracks"):
+            sec[k] = blk2[k]
+        if model is not None:
+            prop = fbl.LearnedStep(model)
+            xt2_dev = torch.from_numpy(xt2.astype(np.float32)).cuda()
+            names = ("learned_bf16", "learned_bf16_sr", "learned_f16", "learned_f32")
+            orders = []
+            for s_off in (2, 3, 4):
+                p2 = syn.view_permutations(g2.n_views, 3 * n_it2, seed=seed2 + s_off)
+                orders.append(rmse_race(fbl, g2, cfg2, b2, xt2_dev, p2,
+                                        [(v, dict(LEARNED_RUNS[v], proposer=prop)) for v in names], warm_s=0.5))
+            sec["time_to_rmse"] = orders[0]
+            sp = {v: [o[v]["speedup"] for o in orders] for v in names}
+            sec["view_orders"] = {"seeds": [seed2 + s for s in (2, 3, 4)], "speedup": sp,
+                                  "median_speedup": {v: (float(np.median(x)) if all(y is not None for y in x)
+                                                         else None) for v, x in sp.items()}}
+            del xt2_dev
+        rec["secondary"] = sec
+        del b2
+        torch.cuda.empty_cache()
     print(json.dumps(rec), flush=True)
     return 0
 
