@@ -590,6 +590,19 @@ def kernel_scaling(fbl, syn, names, reps=5, storage="f32"):
                 fbl.fb_lisa_step(plan, x, gr, 1e-3, 0.0, 0.0, math.inf, xbar=xb, red=red)
             torch.cuda.synchronize()
             kt = plan.timing_read()
+            t_mixed = None
+            if storage != "f32":
+                # the prox trial of the mixed form: FP32 iterate, 16-bit copy (14 bytes per voxel)
+                x32 = x.float()
+                xb32 = torch.empty_like(x32)
+                fbl.fb_lisa_step_mixed(plan, x32, gr, 1e-3, xbar=xb32, xbar16=xb, red=red)
+                plan.timing(True, kernels=("step",))
+                for _ in range(reps):
+                    fbl.fb_lisa_step_mixed(plan, x32, gr, 1e-3, xbar=xb32, xbar16=xb, red=red)
+                torch.cuda.synchronize()
+                ms, n = plan.timing_read()["step"]
+                t_mixed = ms / n * 1e-3
+                del x32, xb32
         t = {k: ms / n * 1e-3 for k, (ms, n) in kt.items() if n}
         byts = B * (g.d * vb + 4 * g.n_p)
         rec = {"workload": "%s: %d^3, %d views, %dx%d detector, batch %d" % (name, g.nx, g.n_views, g.nu, g.nv, B),
@@ -602,6 +615,9 @@ def kernel_scaling(fbl, syn, names, reps=5, storage="f32"):
                "forward_hbm_frac": round(byts / t["forward"] / 8e12, 4),
                "backproject_hbm_frac": round(byts / t["backproject"] / 8e12, 4),
                "step_hbm_frac": round((4 + 2 * vb) * g.d / t["step"] / 8e12, 4)}
+        if t_mixed is not None:
+            rec["step_mixed_us"] = round(t_mixed * 1e6, 1)
+            rec["step_mixed_hbm_frac"] = round(14 * g.d / t_mixed / 8e12, 4)
         log(json.dumps(rec))
         out.append(rec)
         del x, r, y, gr, xb
@@ -628,6 +644,9 @@ def main(argv=None):
                     help="skip the secondary 256^3 block (throughput and a three-order time-to-RMSE comparison)")
     ap.add_argument("--no-cone-fraction", action="store_true",
                     help="skip the cone fraction (one single-view backprojection per view of the batch)")
+    ap.add_argument("--orders", type=int, default=1,
+                    help="view orders of the main time-to-RMSE comparison (seeds base+2, base+3, ...); the median "
+                         "speedup over them is reported (one order by default, to stay within minutes at 1024^3)")
     ap.add_argument("--variants", default="learned_bf16",
                     help="learned runs of the main comparison, comma-separated from %s" % ",".join(LEARNED_RUNS))
     ap.add_argument("--probe", action="store_true",
@@ -739,6 +758,24 @@ def main(argv=None):
         tt = rmse_race(fbl, g, cfg, b_dev, xt_dev, perms, runs)
         tt["proposer"] = "5-64-64-1 perceptron trained on %d iterations of 200 seeded 64^3 runs" % n_samples
         tt["view_order_seed"] = seed + 2
+        if args.orders > 1:
+            names = [v for v, _ in runs]
+            more = []
+            for s_off in range(3, 2 + args.orders):
+                log("time to RMSE at %s, view order %d ..." % (name, s_off))
+                p_o = syn.view_permutations(g.n_views, 3 * n_it, seed=seed + s_off)
+                more.append(rmse_race(fbl, g, cfg, b_dev, xt_dev, p_o, runs))
+            orders = [tt] + more
+            sp = {v: [o[v]["speedup"] for o in orders] for v in names}
+            tt["view_orders"] = {
+                "seeds": [seed + s for s in range(2, 2 + args.orders)], "speedup": sp,
+                "median_speedup": {v: (float(np.median(x)) if all(y is not None for y in x) else None)
+                                   for v, x in sp.items()},
+                "plain_seconds_to_target": [o["plain_f32"]["to_rmse_target"]["seconds"] for o in orders],
+                "rmse_target": [o["rmse_target"] for o in orders],
+                "speedup_to_plain_min": {v: [round(o["plain_f32"]["to_plain_min_rmse"]["seconds"]
+                                                   / o[v]["to_plain_min_rmse"]["seconds"], 3)
+                                             if o[v]["to_plain_min_rmse"] else None for o in orders] for v in names}}
         rec["time_to_rmse"] = tt
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

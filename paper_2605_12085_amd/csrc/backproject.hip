@@ -55,7 +55,11 @@ constexpr int kThreads = 256;
 constexpr int kWinRows = 28;   // staged rows per column (longer spans read global memory)
 constexpr int kSegRows = kWinRows / 4;     // rows per lane: four lanes share a column
 static_assert(kWinRows % 4 == 0, "a column's rows split evenly over four lanes");
-constexpr int kPreStride = kWinRows + 1;   // prefix entries per column (odd: adjacent columns use distinct banks)
+// Prefix entries per column (odd: adjacent columns use distinct banks).  A stride of 31,
+// which spreads a wave's look-ups over more banks, was measured 28% slower: the block's
+// LDS then exceeds a third of the compute unit's in allocation granules, and only two
+// blocks fit per compute unit instead of three.
+constexpr int kPreStride = kWinRows + 1;
 constexpr int kRowCen = kWinRows / 2;      // row origin of the moment prefix (keeps it within 32 bits)
 constexpr int kQuantBits = 22;             // residuals are scaled to at most 2^22 in magnitude
 constexpr int kExpNonFinite = 1 << 20;     // scale exponent marking a column with a non-finite entry
