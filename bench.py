@@ -262,7 +262,7 @@ def rmse_race(fbl, g, cfg, b_f32, xt_dev, perms, runs, warm_s=None):
     class Budget(Exception):
         pass
 
-    def go(name, b_dev, vol_dtype, alpha_init, budget, mixed=False, sr_seed=None):
+    def go(name, b_dev, vol_dtype, alpha_init, budget, mixed=False, sr_seed=None, stop_below=None):
         B = cfg["batch"]
         run = fbl.FBLisa(g, b_dev, n0=B, epochs=cfg["epochs"], lo=cfg["lo"], hi=cfg["hi"], vol_dtype=vol_dtype,
                          sr_seed=sr_seed, n_max=B, mixed=mixed)
@@ -278,6 +278,8 @@ def rmse_race(fbl, g, cfg, b_f32, xt_dev, perms, runs, warm_s=None):
                 log("  %s: iteration %d, %.1f s, rmse %.4e" % (name, len(st["rmse"]), el, e))
             st["excluded"] += time.perf_counter() - t_in
             if budget is not None and el >= budget:
+                raise Budget()
+            if stop_below is not None and e <= stop_below:
                 raise Budget()
 
         warm_clock(fbl, run.plan, run.x16, perms[0][:B], run.r[:B], run.g, warm_s)
@@ -335,9 +337,13 @@ def rmse_race(fbl, g, cfg, b_f32, xt_dev, perms, runs, warm_s=None):
         if spec.get("proj16") and b16 is None:
             b16 = b_f32.half()
         b_dev = b16 if spec.get("proj16") else b_f32
+        # a run marked "until_targets" stops once it has reached both targets (the budget still caps it)
         hist, st = go(name, b_dev, spec["vol_dtype"], spec.get("proposer"), T, mixed=spec.get("mixed", False),
-                      sr_seed=spec.get("sr_seed"))
+                      sr_seed=spec.get("sr_seed"), stop_below=min(target, best) if spec.get("until_targets") else None)
         sm = summary(hist, st)
+        if spec.get("until_targets") and st["t"][-1] < T:
+            sm["at_budget"] = None
+            sm["stopped"] = "after reaching both targets"
         sm["storage"] = spec["label"]
         tp = rec["plain_f32"]["to_rmse_target"]["seconds"]
         sm["speedup"] = (round(tp / sm["to_rmse_target"]["seconds"], 3)
@@ -356,6 +362,9 @@ LEARNED_RUNS = {
                             label="BF16 iterate with stochastic rounding; FP16 data"),
     "learned_f16": dict(vol_dtype="f16", mixed=True, proj16=True,
                         label="projector reads an FP16 copy of the FP32 iterate; FP16 data"),
+    "learned_f16_until": dict(vol_dtype="f16", mixed=True, proj16=True, until_targets=True,
+                              label="projector reads an FP16 copy of the FP32 iterate; FP16 data; stopped once "
+                                    "both targets are reached"),
     "learned_f32": dict(vol_dtype="f32", label="FP32 iterate and data"),
 }
 
@@ -647,7 +656,7 @@ def main(argv=None):
     ap.add_argument("--orders", type=int, default=1,
                     help="view orders of the main time-to-RMSE comparison (seeds base+2, base+3, ...); the median "
                          "speedup over them is reported (one order by default, to stay within minutes at 1024^3)")
-    ap.add_argument("--variants", default="learned_bf16",
+    ap.add_argument("--variants", default="learned_bf16,learned_f16_until",
                     help="learned runs of the main comparison, comma-separated from %s" % ",".join(LEARNED_RUNS))
     ap.add_argument("--probe", action="store_true",
                     help="counter-collection run: 3 forward, 1 backprojection, 1 step call of the workload, then "
