@@ -422,11 +422,16 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                         // at zero weight (see the file's head)
                         const float inv = __builtin_amdgcn_rcpf(rz);
                         const float ub = fmaf(-a0, inv, 1.0f);
-                        const double rzd = (double)rz;
-                        // -(eta of row kRowCen): H(y) = (y - that) P - rz Q with the moment
-                        // prefix taken about row kRowCen
-                        double nam = -fma(rzd, (double)kRowCen, (double)a0);
-                        if (kx == kExpNonFinite) nam = __builtin_nan("");
+                        // H is formed scaled by sc = 2^-kx, which undoes the column's
+                        // quantisation scale (scaling by a power of two commutes with FP64
+                        // rounding, so it costs no accuracy, and the entries need no
+                        // rescaling).  A column with a non-finite entry takes sc = NaN, hence
+                        // NaN entries.
+                        const double sc = kx == kExpNonFinite ? __builtin_nan("") : ldexp(1.0, -kx);
+                        const double rzs = -(double)rz * sc;
+                        // -(eta of row kRowCen), scaled: H(y) = (y - that) P - rz Q with the
+                        // moment prefix taken about row kRowCen
+                        const double nam = -fma((double)rz, (double)kRowCen, (double)a0) * sc;
                         int2 e[kKH + 2];
 #pragma unroll
                         for (int i = 0; i < kKH + 2; ++i) {
@@ -436,14 +441,20 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                         }
                         // all ten look-ups are in flight before the first is used
                         __builtin_amdgcn_sched_barrier(0);
+                        // coefficient of P at y = i - 1, scaled: (y + nam) sc, as a running sum
+                        // (each step rounds at most at 2^-52 of a value below 2^7, far below
+                        // the FP32 rounding of the entries)
+                        double cy = nam - sc;
                         double H[kKH + 2];
 #pragma unroll
-                        for (int i = 0; i < kKH + 2; ++i)
-                            H[i] = fma((double)(i - 1) + nam, (double)e[i].x, -rzd * (double)e[i].y);
+                        for (int i = 0; i < kKH + 2; ++i) {
+                            H[i] = fma(cy, (double)e[i].x, rzs * (double)e[i].y);
+                            cy += sc;
+                        }
 #pragma unroll
                         for (int kk = 0; kk < kKH; ++kk) {
                             const double zd = (H[kk + 2] + H[kk]) - 2.0 * H[kk + 1];
-                            Z[kk * NPM + p] = ldexpf((float)zd, -kx);
+                            Z[kk * NPM + p] = (float)zd;
                         }
                     }
                 } else {

@@ -20,7 +20,9 @@
 //     then row tiles.  A row tile's rays cross one horizontal band of the volume, so the
 //     blocks resident at one time (every view's column tiles of a few row tiles) read the
 //     same band, which the last-level cache then serves to all views of the batch instead
-//     of each view reading the volume from HBM.
+//     of each view reading the volume from HBM.  Within runs of 64 blocks, the 8 blocks
+//     that land on one XCD take 8 consecutive tiles, so neighbouring column tiles (whose
+//     tap rows share cache lines at their edges) read through the same L2.
 #include "common.h"
 #include "device_util.h"
 
@@ -35,6 +37,19 @@ constexpr int kChunk = 16;    // slices per FP64 position refresh and per FP32 p
 constexpr int kThreads = kCols * kWaves;
 constexpr int kFillWaves = 2048;  // two waves per SIMD: below this a launch splits the slice march
 
+// Launch-order index of workgroup b of a grid of n.  The dispatcher deals consecutive
+// workgroups to the chip's 8 XCDs in turn, each with its own L2.  Within every whole run
+// of 64 workgroups this gives the 8 that share an XCD 8 consecutive indices, so tiles
+// that are neighbours in the launch order (and read overlapping cache lines) share an
+// L2, while the 8 XCDs still work on the same 64-tile stretch of the order.  A bijection
+// on [0, n): runs are permuted within themselves and a final partial run is unchanged.
+__device__ __forceinline__ int xcd_grouped_block(int b, int n)
+{
+    if (b >= (n & ~63)) return b;
+    const int w = b & 63;
+    return (b & ~63) + (w & 7) * 8 + (w >> 3);
+}
+
 // Horizontal pair of taps (p, p+1) of one z-row: both at consecutive addresses.
 template <typename TV>
 __device__ __forceinline__ void load_pair(const TV *__restrict__ base, int64_t off, float &a, float &b)
@@ -47,7 +62,8 @@ __device__ __forceinline__ void load_pair(const TV *__restrict__ base, int64_t o
 // z-line it fills: line entry kk holds z = kz + kk; ka is the line origin in the
 // thread's ray coordinates.
 struct SliceState {
-    int64_t row;     // element offset of (slice, p, z = kz)
+    int sp;          // element offset of (slice, p, z = 0); 32 bits hold every offset into
+                     // the volume (the plan admits fewer than 2^31 voxels)
     float wa, wb;
     int ka, kz;
     bool inside;     // z = kz .. kz+KB-1 all inside the volume
@@ -72,10 +88,11 @@ __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
     __shared__ float line[KB * kThreads];
     __shared__ double red[4];
     const int tiles_u = (geo.nu + kCols - 1) / kCols;
+    const int lb = xcd_grouped_block((int)blockIdx.x, (int)gridDim.x);
     // linear block index -> (row tile, view, column tile), column tiles fastest
     const int nbv = (int)gridDim.x / blocks_per_view;          // views in this launch
-    const int rt = (int)blockIdx.x / (nbv * tiles_u);
-    const int rem = (int)blockIdx.x - rt * nbv * tiles_u;
+    const int rt = lb / (nbv * tiles_u);
+    const int rem = lb - rt * nbv * tiles_u;
     const int bi = rem / tiles_u;
     const int tile = rt * tiles_u + (rem - bi * tiles_u);    // tile within the view (column fastest)
     const int view = vl.v[bi];
@@ -103,8 +120,8 @@ __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
     const int na = cp.axis == 0 ? geo.nx : geo.ny;
     const int nb = cp.axis == 0 ? geo.ny : geo.nx;
     const TV *__restrict__ vol = cp.axis == 0 ? xt : x;
-    const int64_t zstride = (int64_t)geo.nx * geo.ny;
-    const int64_t sstride = cp.axis == 0 ? geo.ny : geo.nx;
+    const int zstride = geo.nx * geo.ny;
+    const int sstride = cp.axis == 0 ? geo.ny : geo.nx;
     const float xs = (float)cp.xi1;
     // Rows are equally spaced in eta: row rr0 + r sits at eta = cz + tau * (V0 + r * dvz),
     // with V0 the vertical index slope of row rr0.  Per slice the thread keeps the first
@@ -160,11 +177,11 @@ __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
             S.inside = S.kz >= 0 && S.kz + KB <= geo.nz;
             // a lane whose march ended (fewer slices than the block's longest) keeps
             // addressing its last slice; its ray pass is skipped
-            S.row = (int64_t)min(m0 + s, na - 1) * sstride + p + (int64_t)S.kz * zstride;
+            S.sp = min(m0 + s, na - 1) * sstride + p;
             return S;
         };
         auto load_line = [&](const SliceState &S, LineRegs<TB, KB> &L) {
-            const TV *__restrict__ q = vol + S.row;
+            const TV *__restrict__ q = vol + (S.sp + S.kz * zstride);   // inside: kz >= 0
 #pragma unroll
             for (int kk = 0; kk < KB; ++kk) {
                 L.a[kk] = to_f32(q[0]);
@@ -187,7 +204,7 @@ __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
                     const int k = P.kz + kk;
                     float v = 0.0f;
                     if ((unsigned)k < (unsigned)geo.nz) {
-                        const TV *__restrict__ q = vol + (P.row + (int64_t)kk * zstride);
+                        const TV *__restrict__ q = vol + (P.sp + k * zstride);
                         v = fmaf(P.wb, to_f32(q[1]), P.wa * to_f32(q[0]));
                     }
                     my[kk * kThreads] = v;
