@@ -20,7 +20,8 @@
 //      residual and of the residual times the row index;
 //   3. forms each pair's 8-entry z-profile from those prefix sums (below);
 //   4. lets every thread add to its voxel column (m, q) the profiles of the columns whose
-//      xi lies within one voxel (binary search: xi is monotone along the slice's pairs).
+//      xi lies within one voxel (a contiguous run of the slice's pairs, located from the
+//      columns through (m, q - 1) and (m, q + 1)).
 //
 // Profiles from prefix sums.  The hat is the second difference of the ramp
 // ramp(t) = max(0, t):  hat(e - k) = ramp(k + 1 - e) - 2 ramp(k - e) + ramp(k - 1 - e).
@@ -64,6 +65,68 @@ constexpr int kRowCen = kWinRows / 2;      // row origin of the moment prefix (k
 constexpr int kQuantBits = 22;             // residuals are scaled to at most 2^22 in magnitude
 constexpr int kExpNonFinite = 1 << 20;     // scale exponent marking a column with a non-finite entry
 constexpr int kWinExtra = 16;  // columns the 16 slices' ranges may add to one slice's
+
+// Lane exchanges within a wave64.  A row is 16 consecutive lanes; DPP moves stay within a
+// row, and gfx950's permlane swaps exchange whole rows.
+constexpr int kDppRowShr1 = 0x111;         // row_shr:n is kDppRowShr1 - 1 + n
+constexpr int kDppXor1 = 0xB1;             // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;             // quad_perm [2,3,0,1]
+constexpr int kDppRowHalfMirror = 0x141;   // lane i <-> 7 - i within each half row
+constexpr int kDppRowMirror = 0x140;       // lane i <-> 15 - i within the row
+
+template <int kCtrl>
+__device__ __forceinline__ int dpp(int x)
+{
+    // bound_ctrl: a source lane outside the row reads 0
+    return __builtin_amdgcn_update_dpp(0, x, kCtrl, 0xF, 0xF, true);
+}
+
+// Inclusive prefix sum over the 16 lanes of each row.
+__device__ __forceinline__ int row_inclusive_sum(int x)
+{
+    x += dpp<kDppRowShr1>(x);
+    x += dpp<kDppRowShr1 + 1>(x);
+    x += dpp<kDppRowShr1 + 3>(x);
+    x += dpp<kDppRowShr1 + 7>(x);
+    return x;
+}
+
+// Minimum and maximum over the 16 lanes of each row, in every lane of the row.
+__device__ __forceinline__ int row_min(int x)
+{
+    x = min(x, dpp<kDppXor1>(x));
+    x = min(x, dpp<kDppXor2>(x));
+    x = min(x, dpp<kDppRowHalfMirror>(x));
+    return min(x, dpp<kDppRowMirror>(x));
+}
+__device__ __forceinline__ int row_max(int x)
+{
+    x = max(x, dpp<kDppXor1>(x));
+    x = max(x, dpp<kDppXor2>(x));
+    x = max(x, dpp<kDppRowHalfMirror>(x));
+    return max(x, dpp<kDppRowMirror>(x));
+}
+
+// Maximum over the four lanes l, l ^ 16, l ^ 32, l ^ 48 (the same lane of every row).
+// permlane16_swap(x, x) returns x of the even row of each row pair in its first element
+// and x of the odd row in its second, in both rows; permlane32_swap likewise returns the
+// lower and the upper half's x.
+__device__ __forceinline__ float rows_max(float x)
+{
+    const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    x = fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return fmaxf(__uint_as_float(b[0]), __uint_as_float(b[1]));
+}
+
+// Sum of x over the lanes of rows 0 .. row - 1 at this lane's position in the row.
+__device__ __forceinline__ int rows_exclusive_sum(int x, int row)
+{
+    const auto a = __builtin_amdgcn_permlane16_swap((unsigned)x, (unsigned)x, false, false);
+    const int even = (int)a[0], pair = (int)a[0] + (int)a[1];   // even row's x; the row pair's sum
+    const auto b = __builtin_amdgcn_permlane32_swap((unsigned)pair, (unsigned)pair, false, false);
+    return ((row & 1) ? even : 0) + (row >= 2 ? (int)b[0] : 0);
+}
 
 // rw = grad_scale * w * r: the per-ray path length per slice folded into the residual.
 __global__ __launch_bounds__(256) void prescale_kernel(const float *__restrict__ r, Geo geo, DeviceTables tab,
@@ -190,16 +253,17 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
             // so bounds taken at these two columns hold for all of its pairs.
             const ColParam ca = cols[cl0], cb = cols[cl1];
             __syncthreads();   // the previous class's readers are done with the shared arrays
-            // 1. per-slice column ranges in lanes 0..15 of every wave, each slice's first pair
-            //    (a prefix sum over those lanes) and the class window's columns [c0, c1], the
-            //    union of the slices' ranges (a reduction over them), by lane exchanges.  Every
-            //    wave computes the same values from the same inputs and keeps them in its own
-            //    registers, read by lane index where needed, so none pass through LDS.
+            // 1. per-slice column ranges: lane l of every 16-lane row holds slice l & 15, so
+            //    every row of every wave holds all 16 slices.  Each slice's first pair (a
+            //    prefix sum over the row) and the class window's columns [c0, c1] (the union
+            //    of the slices' ranges, a reduction over the row) come from row-local DPP
+            //    moves; every wave computes the same values from the same inputs and keeps
+            //    them in its own registers, so none pass through LDS.
             int sa, sn, sp, c0, c1, NP;
             {
-                const int mg = mt0 + lane;
+                const int mg = mt0 + (lane & 15);
                 int a = 0, n = 0;
-                if (lane < kTQ && mg < na) {
+                if (mg < na) {
                     const float fm = (float)mg;
                     float u0, u1;
                     if (axis == 0) {
@@ -216,24 +280,14 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                     const int b = min(cl1, (int)ceilf(fminf(hi, (float)geo.nu + 4.0f)) + 1);
                     n = min(WP, max(0, b - a + 1));
                 }
-                int incl = n;   // lanes >= kTQ hold no slice (n = 0)
-#pragma unroll
-                for (int off = 1; off < kTQ; off <<= 1) {
-                    const int t = __shfl_up(incl, off);
-                    if (lane >= off) incl += t;
-                }
-                int lo = n > 0 ? a : INT_MAX, hi = n > 0 ? a + n - 1 : -1;
-#pragma unroll
-                for (int off = 1; off < kTQ; off <<= 1) {   // within aligned groups of kTQ lanes
-                    lo = min(lo, __shfl_xor(lo, off));
-                    hi = max(hi, __shfl_xor(hi, off));
-                }
+                const int incl = row_inclusive_sum(n);
+                const int lo = row_min(n > 0 ? a : INT_MAX), hi = row_max(n > 0 ? a + n - 1 : -1);
                 sa = a;
                 sn = n;
                 sp = incl - n;
-                c0 = __shfl(lo, 0);
-                c1 = __shfl(hi, 0);
-                NP = __shfl(incl, kTQ - 1);
+                c0 = __builtin_amdgcn_readlane(lo, 0);
+                c1 = __builtin_amdgcn_readlane(hi, 0);
+                NP = __builtin_amdgcn_readlane(incl, kTQ - 1);
             }
             if (c1 < 0) continue;   // uniform across the block
             const int nC = c1 - c0 + 1;
@@ -308,8 +362,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                     float mx = 0.0f;
 #pragma unroll
                     for (int j = 0; j < kSegRows; ++j) mx = fmaxf(mx, fabsf(wv[cs][j]));
-                    mx = fmaxf(mx, __shfl_xor(mx, 16));
-                    mx = fmaxf(mx, __shfl_xor(mx, 32));
+                    mx = rows_max(mx);
                     const bool fin = mx <= 3.4028235e38f;   // false for inf and NaN
                     int ex;
                     (void)frexpf(fin ? mx : 1.0f, &ex);      // mx < 2^ex
@@ -324,16 +377,8 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                         ps[j] = P;
                         qs[j] = Q;
                     }
-                    int iP = P, iQ = Q;
-                    {
-                        const int uP = __shfl_up(iP, 16), uQ = __shfl_up(iQ, 16);
-                        if (wseg >= 1) { iP += uP; iQ += uQ; }
-                    }
-                    {
-                        const int uP = __shfl_up(iP, 32), uQ = __shfl_up(iQ, 32);
-                        if (wseg >= 2) { iP += uP; iQ += uQ; }
-                    }
-                    const int oP = iP - P, oQ = iQ - Q;   // sums of the rows below this lane's
+                    // sums of the rows below this lane's (the lanes of rows 0 .. wseg - 1)
+                    const int oP = rows_exclusive_sum(P, wseg), oQ = rows_exclusive_sum(Q, wseg);
                     if (col < nC) {
                         int2 *__restrict__ dst = pre + col * kPreStride;
                         if (wseg == 0) {
@@ -347,21 +392,21 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 }
             };
             if (stg[0]) load_window(0);
-            // Pair tables: the 16 threads of group tid / 16 take the pairs of slice tid / 16,
-            // one in every 16 (kPairIters = WP / 16 rounds cover the slice's at most WP).
+            // Pair tables: thread tid takes the pairs of its lane's slice tid & 15 (whose
+            // range it holds) at column offsets tid / 16 + 16 i (kPairIters = WP / 16 rounds
+            // cover the slice's at most WP).
             static_assert(kThreads == kTQ * 16 && WP % 16 == 0, "16 threads per slice");
-            const int sm = tid >> 4, si = tid & 15;
-            const int sA = __shfl(sa, sm), sN = __shfl(sn, sm), sF = __shfl(sp, sm);
+            const int sm = lane & 15, si = tid >> 4;
             ColParam pc[kPairIters];
 #pragma unroll
             for (int i = 0; i < kPairIters; ++i)
-                if (si + 16 * i < sN) pc[i] = cols[sA + si + 16 * i];
+                if (si + 16 * i < sn) pc[i] = cols[sa + si + 16 * i];
             // 2. pair geometry: xi for the voxel gather, the ray parameter for the profile
 #pragma unroll
             for (int i = 0; i < kPairIters; ++i) {
                 const int cl = si + 16 * i;
-                if (cl < sN) {
-                    const int p = sF + cl;
+                if (cl < sn) {
+                    const int p = sp + cl;
                     const ColParam &cp = pc[i];
                     const double fm = (double)(mt0 + sm);
                     const float xl = (float)(fma(fm, cp.xi1, cp.xi0) - (double)q0);
@@ -374,35 +419,50 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                         const double row0 = stg[h] ? (double)r0h[h] : 0.0;
                         pa0[h][p] = (float)fma(B, row0 - (double)geo.cv, geo.cz - (double)(k0 + h * kKH));
                     }
-                    pcr[p] = (short)(sA + cl - c0);
+                    pcr[p] = (short)(sa + cl - c0);
                 }
             }
             if (stg[0]) build_prefix(0);
             __syncthreads();   // pair tables and the first half's prefix sums complete
             // This thread's voxel column (slice m, in-slice index q) takes the pairs of slice m
-            // whose xi lies within one voxel of q: the first is found by binary search (xi is
-            // monotone along a slice's pairs), the count by a scan; both serve both halves.
+            // whose xi lies within one voxel of q; both halves use them.  The detector column
+            // through a point is monotone along the slice, so those pairs are the columns
+            // between the ones through (m, q - 1) and (m, q + 1): the floor and ceiling of
+            // those two (in FP32, far within a column of the exact values) bound them with at
+            // most two columns to spare at either end, and the spare ones, whose xi as stored
+            // lies a voxel or more from q, are dropped after reading the two outermost of
+            // each end (xi is monotone along a slice's pairs).
             const float gq = (float)(axis == 0 ? tj : ti);
             int gfirst = 0, gcnt = 0;
             {
-                const int m = axis == 0 ? ti : tj;
-                const int n = __shfl(sn, m);
-                gfirst = __shfl(sp, m);
-                const float *__restrict__ xs = xiq + gfirst;
-                if (n > 0) {
-                    const float sgn = (n >= 2 && xs[n - 1] < xs[0]) ? -1.0f : 1.0f;
-                    // first pair with sgn*xi > sgn*q - 1 (sgn*xi increases along the slice)
-                    int lo = 0, hi = n;
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (sgn * xs[mid] > sgn * gq - 1.0f) hi = mid;
-                        else lo = mid + 1;
-                    }
-                    int e = lo;
-                    while (e < n && sgn * xs[e] < sgn * gq + 1.0f) ++e;
-                    gfirst += lo;
-                    gcnt = e - lo;
+                int ga = sa, gn = sn, gp = sp;   // axis 0: the slice is this lane's own, ti
+                if (axis != 0) {                 // axis 1: slice tj, held by lane tj of every row
+                    ga = __shfl(sa, tj);
+                    gn = __shfl(sn, tj);
+                    gp = __shfl(sp, tj);
                 }
+                const float fm = (float)(mt0 + (axis == 0 ? ti : tj));
+                float u0, u1;
+                if (axis == 0) {
+                    const float X = (fm - cxv) * geo.hx;
+                    u0 = column_of(geo, vp, X, ((float)(q0 - 1) + gq - cyv) * geo.hy);
+                    u1 = column_of(geo, vp, X, ((float)(q0 + 1) + gq - cyv) * geo.hy);
+                } else {
+                    const float Y = (fm - cyv) * geo.hy;
+                    u0 = column_of(geo, vp, ((float)(q0 - 1) + gq - cxv) * geo.hx, Y);
+                    u1 = column_of(geo, vp, ((float)(q0 + 1) + gq - cxv) * geo.hx, Y);
+                }
+                int f = max(ga, (int)floorf(fmaxf(fminf(u0, u1), -4.0f)));
+                int l = min(ga + gn - 1, (int)ceilf(fminf(fmaxf(u0, u1), (float)geo.nu + 4.0f)));
+                if (f <= l) {
+                    const float *__restrict__ xs = xiq + (gp - ga);   // xs[c]: xi of column c's pair
+                    const float xf0 = xs[f], xf1 = xs[min(f + 1, l)];
+                    const float xl0 = xs[l], xl1 = xs[max(l - 1, f)];
+                    f += fabsf(xf0 - gq) < 1.0f ? 0 : fabsf(xf1 - gq) < 1.0f ? 1 : 2;
+                    l -= fabsf(xl0 - gq) < 1.0f ? 0 : fabsf(xl1 - gq) < 1.0f ? 1 : 2;
+                }
+                gfirst = gp + (f - ga);
+                gcnt = max(0, l - f + 1);
             }
 
             // 3. profiles of the pairs that meet the tile, for half h

@@ -11,6 +11,8 @@ Checked:
   * every detector row with nonzero weight on a half tile lies inside the staged row
     window of that half;
   * every staged or fallback residual address lies inside the view's residual rows;
+  * each voxel column's gather range is exactly the run of its slice's pairs within one
+    voxel of it;
   * an empty (slice, column) pass is skipped before any window is formed.
 The larger workloads are checked on tiles sampled at the corners, the centre and the top
 and bottom of the volume, where the row windows are tallest."""
@@ -95,6 +97,48 @@ def _wp_of_plan(g, cols, split):
     return next((sz for sz in (32, 48, 64) if need <= sz), None)
 
 
+def _check_gather_ranges(g, cols, v, c, s, axis, ms, q0, a, n, cxv, cyv, stats):
+    """Each voxel column (slice m, in-slice index q) gathers the pairs of slice m between
+    the floor and the ceiling of the detector columns through (m, q - 1) and (m, q + 1),
+    clamped to the slice's range, after dropping up to two columns at either end whose
+    stored xi (FP32) lies a voxel or more from q.  Checked: the valid pairs (|xi - q| < 1)
+    form one run inside the candidate range with at most two spare columns at either end,
+    so the kernel's range is exactly that run."""
+    q = np.arange(TQ, dtype=F32)[None, :]
+    fm = ms.astype(F32)[:, None]
+    lo_q = ((F32(q0 - 1) + q) - (cyv if axis == 0 else cxv)).astype(F32)
+    hi_q = ((F32(q0 + 1) + q) - (cyv if axis == 0 else cxv)).astype(F32)
+    if axis == 0:
+        X = np.broadcast_to(((fm - cxv) * F32(g.hx)).astype(F32), (len(ms), TQ))
+        u0 = _col_of(g, c, s, X, np.broadcast_to((lo_q * F32(g.hy)).astype(F32), X.shape))
+        u1 = _col_of(g, c, s, X, np.broadcast_to((hi_q * F32(g.hy)).astype(F32), X.shape))
+    else:
+        Y = np.broadcast_to(((fm - cyv) * F32(g.hy)).astype(F32), (len(ms), TQ))
+        u0 = _col_of(g, c, s, np.broadcast_to((lo_q * F32(g.hx)).astype(F32), Y.shape), Y)
+        u1 = _col_of(g, c, s, np.broadcast_to((hi_q * F32(g.hx)).astype(F32), Y.shape), Y)
+    f = np.maximum(a[:, None], np.floor(np.maximum(np.minimum(u0, u1), -4.0)).astype(np.int64))
+    l = np.minimum((a + n - 1)[:, None], np.ceil(np.minimum(np.maximum(u0, u1), g.nu + 4.0)).astype(np.int64))
+    for im, m in enumerate(ms):
+        if n[im] == 0:
+            assert np.all(f[im] > l[im])
+            continue
+        cc = np.arange(a[im], a[im] + n[im])
+        xi = (cols["xi0"][v, cc] + float(m) * cols["xi1"][v, cc] - q0).astype(F32)
+        valid = np.abs(xi[None, :] - np.arange(TQ, dtype=F32)[:, None]) < F32(1.0)   # [q][column]
+        cnt = valid.sum(axis=1)
+        none = cnt == 0
+        assert np.all(l[im][none] - f[im][none] + 1 <= 4), (v, m)
+        first = cc[np.argmax(valid, axis=1)]
+        last = cc[n[im] - 1 - np.argmax(valid[:, ::-1], axis=1)]
+        some = ~none
+        assert np.all((last - first + 1)[some] == cnt[some]), (v, m)             # one run
+        assert np.all(f[im][some] <= first[some]) and np.all(l[im][some] >= last[some]), (v, m)
+        spare = np.maximum(first - f[im], l[im] - last)[some]
+        if spare.size:
+            assert spare.max() <= 2, (v, m, int(spare.max()))
+            stats["gather_spare_max"] = max(stats.get("gather_spare_max", 0), int(spare.max()))
+
+
 def _check_tiles(g, cols, split, WP, tiles, views, check_cover=True):
     """Replay bp_kernel's set-up for the given tiles (list of (i0, j0, k0)) and views."""
     cxv, cyv = F32(0.5 * (g.nx - 1)), F32(0.5 * (g.ny - 1))
@@ -102,6 +146,7 @@ def _check_tiles(g, cols, split, WP, tiles, views, check_cover=True):
     dvz = g.dv / g.hz
     npix = g.nu * g.nv
     stats = {"passes": 0, "staged": 0, "fallback": 0, "skipped_empty": 0}
+    gathered = set()
     for bi, v in enumerate(views):
         c, s = F32(math.cos(g.angles[v])), F32(math.sin(g.angles[v]))
         a0 = cols["axis"][v, 0]
@@ -154,6 +199,9 @@ def _check_tiles(g, cols, split, WP, tiles, views, check_cover=True):
                     near = (xi > -1.0) & (xi < TQ)
                     inside = (cc[None, :] >= a[:, None]) & (cc[None, :] < (a + n)[:, None])
                     assert np.all(inside | ~near), (v, i0, j0, k0)
+                    if (v, i0, j0, cls) not in gathered:   # the gather ranges do not depend on z
+                        gathered.add((v, i0, j0, cls))
+                        _check_gather_ranges(g, cols, v, c, s, axis, ms, q0, a, n, cxv, cyv, stats)
                 # row windows of the two halves, from the class's outermost columns
                 mA, mB = float(mt0), float(min(mt0 + TQ - 1, na - 1))
                 ts = [mA * cols["t1"][v, cl] + cols["t0"][v, cl] for cl in (cl0, cl1)] + \
