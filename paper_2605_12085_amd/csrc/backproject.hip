@@ -64,6 +64,7 @@ constexpr int kPreStride = kWinRows + 1;
 constexpr int kRowCen = kWinRows / 2;      // row origin of the moment prefix (keeps it within 32 bits)
 constexpr int kQuantBits = 22;             // residuals are scaled to at most 2^22 in magnitude
 constexpr int kExpNonFinite = 1 << 20;     // scale exponent marking a column with a non-finite entry
+constexpr float kRoundMagic = 12582912.0f; // 1.5 * 2^23
 constexpr int kWinExtra = 16;  // columns the 16 slices' ranges may add to one slice's
 
 // Lane exchanges within a wave64.  A row is 16 consecutive lanes; DPP moves stay within a
@@ -107,16 +108,17 @@ __device__ __forceinline__ int row_max(int x)
     return max(x, dpp<kDppRowMirror>(x));
 }
 
-// Maximum over the four lanes l, l ^ 16, l ^ 32, l ^ 48 (the same lane of every row).
+// Maximum over the four lanes l, l ^ 16, l ^ 32, l ^ 48 (the same lane of every row), NaN
+// if any of them is NaN.
 // permlane16_swap(x, x) returns x of the even row of each row pair in its first element
 // and x of the odd row in its second, in both rows; permlane32_swap likewise returns the
 // lower and the upper half's x.
 __device__ __forceinline__ float rows_max(float x)
 {
     const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-    x = fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+    x = __builtin_elementwise_maximum(__uint_as_float(a[0]), __uint_as_float(a[1]));
     const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-    return fmaxf(__uint_as_float(b[0]), __uint_as_float(b[1]));
+    return __builtin_elementwise_maximum(__uint_as_float(b[0]), __uint_as_float(b[1]));
 }
 
 // Sum of x over the lanes of rows 0 .. row - 1 at this lane's position in the row.
@@ -146,8 +148,9 @@ __global__ __launch_bounds__(256) void prescale_kernel(const float *__restrict__
 }
 
 // Detector column index (fractional) of the ray through the point (X, Y) mm (any z).
-// Only column ranges with a column of margin are built from it, so the hardware
-// reciprocal (within a few units in the last place) serves instead of a division.
+// Column ranges are built from its floor and ceiling, which tolerate any error below one
+// column, so the hardware reciprocal (within a few units in the last place) serves
+// instead of a division.
 __device__ __forceinline__ float column_of(const Geo &geo, const ViewParam &vp, float X, float Y)
 {
     const float lat = -X * vp.s + Y * vp.c;
@@ -220,9 +223,11 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
 #pragma unroll
     for (int kk = 0; kk < kTK; ++kk) acc[kk] = 0.0f;
 
+    ViewParam vp_next = tab.view[vl.v[0]];   // loaded a view ahead
     for (int bi = 0; bi < nb; ++bi) {
         const int view = vl.v[bi];
-        const ViewParam vp = tab.view[view];
+        const ViewParam vp = vp_next;
+        if (bi + 1 < nb) vp_next = tab.view[vl.v[bi + 1]];
         const ColParam *__restrict__ cols = tab.col + (int64_t)view * geo.nu;
         const float *__restrict__ rwv = rw + (int64_t)(first + bi) * geo.np;
         // columns whose ray plane crosses the tile's xy square grown by one voxel
@@ -275,9 +280,12 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                         u0 = column_of(geo, vp, ((float)(q0 - 1) - cxv) * geo.hx, Y);
                         u1 = column_of(geo, vp, ((float)(q0 + kTQ) - cxv) * geo.hx, Y);
                     }
+                    // the columns strictly between u0 and u1 cross the slice within one voxel
+                    // of the tile; u is within far less than a column of its exact value, so
+                    // the floor and the ceiling of the two bound them
                     const float lo = fminf(u0, u1), hi = fmaxf(u0, u1);
-                    a = max(cl0, (int)floorf(fmaxf(lo, -4.0f)) - 1);
-                    const int b = min(cl1, (int)ceilf(fminf(hi, (float)geo.nu + 4.0f)) + 1);
+                    a = max(cl0, (int)floorf(fmaxf(lo, -4.0f)));
+                    const int b = min(cl1, (int)ceilf(fminf(hi, (float)geo.nu + 4.0f)));
                     n = min(WP, max(0, b - a + 1));
                 }
                 const int incl = row_inclusive_sum(n);
@@ -359,18 +367,26 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                         const bool keep = col < nC && wseg * kSegRows + j < nRh[h];
                         wv[cs][j] = keep ? wv[cs][j] : 0.0f;
                     }
+                    // largest magnitude, NaN if any entry is NaN (IEEE maximum propagates it)
                     float mx = 0.0f;
 #pragma unroll
-                    for (int j = 0; j < kSegRows; ++j) mx = fmaxf(mx, fabsf(wv[cs][j]));
+                    for (int j = 0; j < kSegRows; ++j) mx = __builtin_elementwise_maximum(mx, fabsf(wv[cs][j]));
                     mx = rows_max(mx);
                     const bool fin = mx <= 3.4028235e38f;   // false for inf and NaN
                     int ex;
                     (void)frexpf(fin ? mx : 1.0f, &ex);      // mx < 2^ex
-                    const int kx = kQuantBits - ex;
+                    // 2^kx, kept a normal FP32 number: only a column whose entries all lie
+                    // below 2^-105 in magnitude is quantised more coarsely than 2^-22 of its
+                    // largest (at 2^-127 absolute)
+                    const int kx = min(kQuantBits - ex, 127);
+                    const float scl = ldexpf(1.0f, kx);
                     int P = 0, Q = 0, ps[kSegRows], qs[kSegRows];
 #pragma unroll
                     for (int j = 0; j < kSegRows; ++j) {
-                        const int q = fin ? (int)rintf(ldexpf(wv[cs][j], kx)) : 0;
+                        // round(v 2^kx) for |v 2^kx| < 2^22: adding 1.5 2^23 leaves it in
+                        // [2^23, 2^24], where FP32 steps by one, so the bits count the integer
+                        // (entries of a non-finite column give garbage; the column is marked)
+                        const int q = __float_as_int(fmaf(wv[cs][j], scl, kRoundMagic)) - __float_as_int(kRoundMagic);
                         P += q;
                         // |row - kRowCen| <= 14 and |q| <= 2^22 both fit 24 bits: a 24-bit product
                         Q += __mul24(wseg * kSegRows + j - kRowCen, q);

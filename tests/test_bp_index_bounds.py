@@ -180,8 +180,8 @@ def _check_tiles(g, cols, split, WP, tiles, views, check_cover=True):
                     u0 = _col_of(g, c, s, np.full_like(Y, F32(q0 - 1 - cxv) * F32(g.hx)), Y)
                     u1 = _col_of(g, c, s, np.full_like(Y, F32(q0 + TQ - cxv) * F32(g.hx)), Y)
                 lo, hi = np.minimum(u0, u1), np.maximum(u0, u1)
-                a = np.maximum(cl0, np.floor(np.maximum(lo, -4.0)).astype(np.int64) - 1)
-                b = np.minimum(cl1, np.ceil(np.minimum(hi, g.nu + 4.0)).astype(np.int64) + 1)
+                a = np.maximum(cl0, np.floor(np.maximum(lo, -4.0)).astype(np.int64))
+                b = np.minimum(cl1, np.ceil(np.minimum(hi, g.nu + 4.0)).astype(np.int64))
                 # the table holds WP pairs per slice: a wider range would be cut silently
                 assert np.all(b - a + 1 <= WP), (v, i0, j0, k0, int((b - a + 1).max()), WP)
                 n = np.minimum(WP, np.maximum(0, b - a + 1))

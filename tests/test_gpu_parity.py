@@ -122,6 +122,29 @@ def test_backproject_c1_all_voxels(fbl, orc):
     _cmp_vol(gg, ref, what="backprojection c1")
 
 
+def test_backproject_non_finite_residual(fbl, orc):
+    # an inf and a NaN residual: every voxel the oracle's gradient makes non-finite is
+    # non-finite on the GPU too (the GPU marks the whole z-profile of the bad detector
+    # column, a superset), and every voxel the GPU leaves finite agrees with the oracle
+    g = ODD
+    print("case backprojection non-finite residual", flush=True)
+    rng = np.random.default_rng(61)
+    views = np.array([0, 5, 9], dtype=np.int32)
+    r = rng.standard_normal((len(views), g.nv, g.nu)).astype(np.float32)
+    r[0, g.nv // 2, g.nu // 2] = np.inf
+    r[2, g.nv // 3, g.nu // 4] = np.nan
+    ref = g.n_views / len(views) * orc.backproject(g, r.astype(np.float64), views)
+    with fbl.Plan(g) as plan:
+        gg = fbl.fb_lisa_backproject(plan, _t(r), views).cpu().numpy().astype(np.float64)
+    bad_ref, bad_gpu = ~np.isfinite(ref), ~np.isfinite(gg)
+    assert bad_ref.any()
+    assert np.all(bad_gpu[bad_ref])
+    ok = ~bad_gpu
+    assert ok.any()
+    err = np.abs(gg[ok] - ref[ok]).max() / np.abs(ref[ok]).max()
+    assert err <= TOL, "finite voxels: rel max %.3g" % err
+
+
 def test_fine_detector_rows_forward_and_backprojection(fbl, orc):
     # detector rows 0.6 voxel apart at the detector (about 0.3 voxel at the volume): the
     # backprojection's residual window for half a tile's z-range exceeds its LDS window on
