@@ -558,7 +558,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 constexpr int h = decltype(hc)::value;
                 // (the search admits only pairs with |xi - q| < 1; the clamp keeps a weight
                 // rounded at that edge from turning negative)
-#pragma unroll 2
+#pragma unroll 1
                 for (int j = 0; j < gcnt; ++j) {
                     const int pp = gfirst + j;
                     const float w = fmaxf(1.0f - fabsf(xiq[pp] - gq), 0.0f);
