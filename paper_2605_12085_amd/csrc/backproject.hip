@@ -486,10 +486,15 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 constexpr int h = decltype(hc)::value;
                 if (stg[h]) {
                     for (int p = tid; p < NP; p += kThreads) {
-                        const float rz = prz[p];
-                        if (rz == 0.0f) continue;   // xi misses the tile: no voxel reads this pair
+                        // A pair whose xi misses the tile (rz = 0) is read by no voxel; its
+                        // profile is formed anyway (with rz = 1, so that every look-up stays in
+                        // the window) rather than branched around: a wave skips a pair only if
+                        // all its lanes do, and the branch would wait on rz before reading the
+                        // pair's other entries.
+                        const float rz0 = prz[p];
                         const float a0 = pa0[h][p];
                         const int col = pcr[p];
+                        const float rz = rz0 == 0.0f ? 1.0f : rz0;
                         const int kx = pexp[col];
                         const int2 *__restrict__ pc = pre + col * kPreStride;
                         // T(y) = ceil((y - a0) / rz) clamped to the window, taken as the
