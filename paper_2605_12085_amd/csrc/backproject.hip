@@ -65,6 +65,7 @@ constexpr int kRowCen = kWinRows / 2;      // row origin of the moment prefix (k
 constexpr int kQuantBits = 22;             // residuals are scaled to at most 2^22 in magnitude
 constexpr int kExpNonFinite = 1 << 20;     // scale exponent marking a column with a non-finite entry
 constexpr float kRoundMagic = 12582912.0f; // 1.5 * 2^23
+constexpr int kBufferFlags = 0x00020000;   // word 3 of a raw gfx9 buffer resource (32-bit data)
 constexpr int kWinExtra = 16;  // columns the 16 slices' ranges may add to one slice's
 
 // Lane exchanges within a wave64.  A row is 16 consecutive lanes; DPP moves stay within a
@@ -230,34 +231,19 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
         if (bi + 1 < nb) vp_next = tab.view[vl.v[bi + 1]];
         const ColParam *__restrict__ cols = tab.col + (int64_t)view * geo.nu;
         const float *__restrict__ rwv = rw + (int64_t)(first + bi) * geo.np;
-        // columns whose ray plane crosses the tile's xy square grown by one voxel
-        float umin = 3.0e38f, umax = -3.0e38f;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float X = ((float)((q & 1) ? i0 + kTQ : i0 - 1) - cxv) * geo.hx;
-            const float Y = ((float)((q & 2) ? j0 + kTQ : j0 - 1) - cyv) * geo.hy;
-            const float u = column_of(geo, vp, X, Y);
-            umin = fminf(umin, u);
-            umax = fmaxf(umax, u);
-        }
-        const int cT0 = max(0, (int)floorf(fmaxf(umin, -4.0f)) - 1);
-        const int cT1 = min(geo.nu - 1, (int)ceilf(fminf(umax, (float)geo.nu + 4.0f)) + 1);
-        if (cT0 > cT1) continue;   // uniform across the block
-        // columns [0, split) march slices of axis_first, the rest the other axis
+        // the view's residual as a buffer: reads past its end return 0
+        const __amdgpu_buffer_rsrc_t rwv_rsrc =
+            __builtin_amdgcn_make_buffer_rsrc((void *)rwv, (short)0, (int)(geo.np * 4), kBufferFlags);
+        // columns [0, split) march slices of axis_first, the rest the other axis (a view
+        // whose fan crosses a diagonal has two classes, any other view one)
         for (int cls = 0; cls < 2; ++cls) {
             const int axis = cls == 0 ? vp.axis_first : 1 - vp.axis_first;
-            const int cl0 = cls == 0 ? cT0 : max(cT0, vp.split);
-            const int cl1 = cls == 0 ? min(cT1, vp.split - 1) : cT1;
+            const int cl0 = cls == 0 ? 0 : vp.split;
+            const int cl1 = cls == 0 ? vp.split - 1 : geo.nu - 1;
             if (cl0 > cl1) continue;
             const int na = axis == 0 ? geo.nx : geo.ny;
             const int mt0 = axis == 0 ? i0 : j0;       // first slice of the tile
             const int q0 = axis == 0 ? j0 : i0;        // first in-slice index of the tile
-            // The class's outermost columns, read before the slices' column ranges are known
-            // so that the loads overlap that step and its barrier.  Every pair of the class
-            // lies within [cl0, cl1], and its ray parameter is monotone along a detector row,
-            // so bounds taken at these two columns hold for all of its pairs.
-            const ColParam ca = cols[cl0], cb = cols[cl1];
-            __syncthreads();   // the previous class's readers are done with the shared arrays
             // 1. per-slice column ranges: lane l of every 16-lane row holds slice l & 15, so
             //    every row of every wave holds all 16 slices.  Each slice's first pair (a
             //    prefix sum over the row) and the class window's columns [c0, c1] (the union
@@ -297,8 +283,23 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 c1 = __builtin_amdgcn_readlane(hi, 0);
                 NP = __builtin_amdgcn_readlane(incl, kTQ - 1);
             }
-            if (c1 < 0) continue;   // uniform across the block
+            if (c1 < 0) continue;   // no ray of the class crosses the tile (uniform across the block)
             const int nC = c1 - c0 + 1;
+            // Every pair lies within the window's columns [c0, c1], and the ray parameter is
+            // monotone along a detector row, so bounds taken at these two columns hold for
+            // all pairs.
+            const ColParam ca = cols[c0], cb = cols[c1];
+            // Pair tables: thread tid takes the pairs of its lane's slice tid & 15 (whose
+            // range it holds) at column offsets tid / 16 + 16 i (kPairIters = WP / 16 rounds
+            // cover the slice's at most WP).  Their column parameters are loaded with the two
+            // above, so that the latencies overlap.
+            static_assert(kThreads == kTQ * 16 && WP % 16 == 0, "16 threads per slice");
+            const int sm = lane & 15, si = tid >> 4;
+            ColParam pc[kPairIters];
+#pragma unroll
+            for (int i = 0; i < kPairIters; ++i)
+                if (si + 16 * i < sn) pc[i] = cols[sa + si + 16 * i];
+            __syncthreads();   // the previous class's readers are done with the shared arrays
             // bounds of the ray parameter over the class's pairs: tau is monotone along a
             // detector row (inversely proportional to the column's D_a, which is affine in
             // the column) and affine in the slice, so over columns [cl0, cl1] and the tile's
@@ -335,23 +336,21 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
             // kSegRows consecutive rows.
             const int wcol = (lane & 15) + 16 * wave, wseg = lane >> 4;
             float wv[kColSweeps][kSegRows];
-            // Loads are unconditional, from a clamped (always valid) row and column, so that
-            // they issue back to back without branches and stay in flight until the prefix
-            // sums use them; build_prefix masks the clamped entries.  A clamped load repeats
-            // an entry of the same column's window (or reads a column that is not kept), so
-            // a non-finite value it brings in belongs to that window anyway.
+            // Loads are unconditional buffer loads, so that they issue back to back without
+            // branches or address arithmetic and stay in flight until the prefix sums use
+            // them: a row or column outside the window reads a neighbouring entry of the
+            // view's residual, or 0 past its end, and build_prefix masks it before any
+            // arithmetic (so a non-finite value outside the window never reaches it).
             auto load_window = [&](int h) {
-                const int lim = (nRh[h] - 1) * geo.nu;
-                const float *__restrict__ rowbase = rwv + (int64_t)r0h[h] * geo.nu + c0;
+                // byte offset of this lane's first entry in the view's residual; rows step by a
+                // uniform offset (scalar registers)
+                const int vo = ((r0h[h] + wseg * kSegRows) * geo.nu + c0 + wcol) * 4;
 #pragma unroll
                 for (int cs = 0; cs < kColSweeps; ++cs) {
-                    const float *__restrict__ src = rowbase + min(wcol + 64 * cs, nC - 1);
-                    int off = wseg * kSegRows * geo.nu;
 #pragma unroll
-                    for (int j = 0; j < kSegRows; ++j) {
-                        wv[cs][j] = src[min(off, lim)];
-                        off += geo.nu;
-                    }
+                    for (int j = 0; j < kSegRows; ++j)
+                        wv[cs][j] = __uint_as_float(
+                            __builtin_amdgcn_raw_buffer_load_b32(rwv_rsrc, vo + 256 * cs, j * geo.nu * 4, 0));
                 }
             };
             // Prefix sums of the loaded window: the column's scale exponent from its largest
@@ -408,15 +407,6 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 }
             };
             if (stg[0]) load_window(0);
-            // Pair tables: thread tid takes the pairs of its lane's slice tid & 15 (whose
-            // range it holds) at column offsets tid / 16 + 16 i (kPairIters = WP / 16 rounds
-            // cover the slice's at most WP).
-            static_assert(kThreads == kTQ * 16 && WP % 16 == 0, "16 threads per slice");
-            const int sm = lane & 15, si = tid >> 4;
-            ColParam pc[kPairIters];
-#pragma unroll
-            for (int i = 0; i < kPairIters; ++i)
-                if (si + 16 * i < sn) pc[i] = cols[sa + si + 16 * i];
             // 2. pair geometry: xi for the voxel gather, the ray parameter for the profile
 #pragma unroll
             for (int i = 0; i < kPairIters; ++i) {
