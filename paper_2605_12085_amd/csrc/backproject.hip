@@ -63,7 +63,6 @@ static_assert(kWinRows % 4 == 0, "a column's rows split evenly over four lanes")
 constexpr int kPreStride = kWinRows + 1;
 constexpr int kRowCen = kWinRows / 2;      // row origin of the moment prefix (keeps it within 32 bits)
 constexpr int kQuantBits = 22;             // residuals are scaled to at most 2^22 in magnitude
-constexpr int kExpNonFinite = 1 << 20;     // scale exponent marking a column with a non-finite entry
 constexpr float kRoundMagic = 12582912.0f; // 1.5 * 2^23
 constexpr int kBufferFlags = 0x00020000;   // word 3 of a raw gfx9 buffer resource (32-bit data)
 constexpr int kWinExtra = 16;  // columns the 16 slices' ranges may add to one slice's
@@ -207,7 +206,8 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                                                       // half's first z (window row 0 if staged, else detector row 0)
     __shared__ short pcr[NPM];                        // the pair's column minus the class window's c0
     __shared__ int2 pre[kWinCols * kPreStride];       // per window column and T: (P(T), Q(T)), integers
-    __shared__ int pexp[kWinCols];                    // per window column: residual scale exponent
+    __shared__ double psc[kWinCols];                  // per window column: 2^-(residual scale exponent),
+                                                      // NaN for a column with a non-finite entry
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -328,6 +328,9 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                 nRh[h] = min(geo.nv - 1, (int)ceilf(rhi) + 1) - r0h[h] + 1;
                 stg[h] = nRh[h] > 0 && nRh[h] <= kWinRows && nC <= kWinCols;
             }
+            // no detector row reaches the tile's z-range (a tile above or below the view's
+            // cone): nothing to add (uniform across the block)
+            if (nRh[0] <= 0 && nRh[1] <= 0) continue;
             // The pairs' column parameters and the first half's residual window are loaded
             // together, before either is used; the second half's window is loaded after
             // the first half's profiles, so that it arrives during that half's gather.
@@ -398,7 +401,7 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                         int2 *__restrict__ dst = pre + col * kPreStride;
                         if (wseg == 0) {
                             dst[0] = make_int2(0, 0);
-                            pexp[col] = fin ? kx : kExpNonFinite;
+                            psc[col] = fin ? ldexp(1.0, -kx) : __builtin_nan("");
                         }
 #pragma unroll
                         for (int j = 0; j < kSegRows; ++j)
@@ -485,7 +488,6 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                         const float a0 = pa0[h][p];
                         const int col = pcr[p];
                         const float rz = rz0 == 0.0f ? 1.0f : rz0;
-                        const int kx = pexp[col];
                         const int2 *__restrict__ pc = pre + col * kPreStride;
                         // T(y) = ceil((y - a0) / rz) clamped to the window, taken as the
                         // truncation of (y - a0) / rz + 1 (one more only where a row sits
@@ -493,12 +495,12 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                         // at zero weight (see the file's head)
                         const float inv = __builtin_amdgcn_rcpf(rz);
                         const float ub = fmaf(-a0, inv, 1.0f);
-                        // H is formed scaled by sc = 2^-kx, which undoes the column's
-                        // quantisation scale (scaling by a power of two commutes with FP64
+                        // H is formed scaled by the column's sc = 2^-kx (psc), which undoes
+                        // its quantisation scale (scaling by a power of two commutes with FP64
                         // rounding, so it costs no accuracy, and the entries need no
-                        // rescaling).  A column with a non-finite entry takes sc = NaN, hence
+                        // rescaling).  A column with a non-finite entry has sc = NaN, hence
                         // NaN entries.
-                        const double sc = kx == kExpNonFinite ? __builtin_nan("") : ldexp(1.0, -kx);
+                        const double sc = psc[col];
                         const double rzs = -(double)rz * sc;
                         // -(eta of row kRowCen), scaled: H(y) = (y - that) P - rz Q with the
                         // moment prefix taken about row kRowCen
