@@ -234,12 +234,26 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
         // the view's residual as a buffer: reads past its end return 0
         const __amdgpu_buffer_rsrc_t rwv_rsrc =
             __builtin_amdgcn_make_buffer_rsrc((void *)rwv, (short)0, (int)(geo.np * 4), kBufferFlags);
+        // columns whose ray plane crosses the tile's xy square grown by one voxel (with a
+        // column of margin): they bound the row windows below
+        float umin = 3.0e38f, umax = -3.0e38f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float X = ((float)((q & 1) ? i0 + kTQ : i0 - 1) - cxv) * geo.hx;
+            const float Y = ((float)((q & 2) ? j0 + kTQ : j0 - 1) - cyv) * geo.hy;
+            const float u = column_of(geo, vp, X, Y);
+            umin = fminf(umin, u);
+            umax = fmaxf(umax, u);
+        }
+        const int cT0 = max(0, (int)floorf(fmaxf(umin, -4.0f)) - 1);
+        const int cT1 = min(geo.nu - 1, (int)ceilf(fminf(umax, (float)geo.nu + 4.0f)) + 1);
+        if (cT0 > cT1) continue;   // uniform across the block
         // columns [0, split) march slices of axis_first, the rest the other axis (a view
         // whose fan crosses a diagonal has two classes, any other view one)
         for (int cls = 0; cls < 2; ++cls) {
             const int axis = cls == 0 ? vp.axis_first : 1 - vp.axis_first;
-            const int cl0 = cls == 0 ? 0 : vp.split;
-            const int cl1 = cls == 0 ? vp.split - 1 : geo.nu - 1;
+            const int cl0 = cls == 0 ? cT0 : max(cT0, vp.split);
+            const int cl1 = cls == 0 ? min(cT1, vp.split - 1) : cT1;
             if (cl0 > cl1) continue;
             const int na = axis == 0 ? geo.nx : geo.ny;
             const int mt0 = axis == 0 ? i0 : j0;       // first slice of the tile
@@ -285,10 +299,10 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
             }
             if (c1 < 0) continue;   // no ray of the class crosses the tile (uniform across the block)
             const int nC = c1 - c0 + 1;
-            // Every pair lies within the window's columns [c0, c1], and the ray parameter is
+            // Every pair lies within the class's columns [cl0, cl1], and the ray parameter is
             // monotone along a detector row, so bounds taken at these two columns hold for
             // all pairs.
-            const ColParam ca = cols[c0], cb = cols[c1];
+            const ColParam ca = cols[cl0], cb = cols[cl1];
             // Pair tables: thread tid takes the pairs of its lane's slice tid & 15 (whose
             // range it holds) at column offsets tid / 16 + 16 i (kPairIters = WP / 16 rounds
             // cover the slice's at most WP).  Their column parameters are loaded with the two

@@ -151,10 +151,20 @@ def _check_tiles(g, cols, split, WP, tiles, views, check_cover=True):
         c, s = F32(math.cos(g.angles[v])), F32(math.sin(g.angles[v]))
         a0 = cols["axis"][v, 0]
         for (i0, j0, k0) in tiles:
+            corners = []
+            for q in range(4):
+                X = F32((i0 + TQ if q & 1 else i0 - 1) - cxv) * F32(g.hx)
+                Y = F32((j0 + TQ if q & 2 else j0 - 1) - cyv) * F32(g.hy)
+                corners.append(float(_col_of(g, c, s, np.asarray(X, F32), np.asarray(Y, F32))))
+            umin, umax = min(corners), max(corners)
+            cT0 = max(0, int(math.floor(max(umin, -4.0))) - 1)
+            cT1 = min(g.nu - 1, int(math.ceil(min(umax, g.nu + 4.0))) + 1)
+            if cT0 > cT1:
+                continue
             for cls in range(2):
                 axis = a0 if cls == 0 else 1 - a0
-                cl0 = 0 if cls == 0 else split[v]
-                cl1 = split[v] - 1 if cls == 0 else g.nu - 1
+                cl0 = cT0 if cls == 0 else max(cT0, split[v])
+                cl1 = min(cT1, split[v] - 1) if cls == 0 else cT1
                 if cl0 > cl1:
                     continue
                 na = g.nx if axis == 0 else g.ny
@@ -192,10 +202,10 @@ def _check_tiles(g, cols, split, WP, tiles, views, check_cover=True):
                     if (v, i0, j0, cls) not in gathered:   # the gather ranges do not depend on z
                         gathered.add((v, i0, j0, cls))
                         _check_gather_ranges(g, cols, v, c, s, axis, ms, q0, a, n, cxv, cyv, stats)
-                # row windows of the two halves, from the window's outermost columns
+                # row windows of the two halves, from the class's outermost columns
                 mA, mB = float(mt0), float(min(mt0 + TQ - 1, na - 1))
-                ts = [mA * cols["t1"][v, cl] + cols["t0"][v, cl] for cl in (c0, c1)] + \
-                     [mB * cols["t1"][v, cl] + cols["t0"][v, cl] for cl in (c0, c1)]
+                ts = [mA * cols["t1"][v, cl] + cols["t0"][v, cl] for cl in (cl0, cl1)] + \
+                     [mB * cols["t1"][v, cl] + cols["t0"][v, cl] for cl in (cl0, cl1)]
                 imin = F32(1.0) / F32(max(ts) * dvz)
                 imax = F32(1.0) / F32(min(ts) * dvz)
                 for h in range(2):
