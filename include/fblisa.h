@@ -88,7 +88,7 @@ typedef struct {
 typedef struct fbl_plan fbl_plan;
 
 /* Host-only geometry validation; touches no device.  Checks: every count >= 1 (each at
- * most 2^24) and nx*ny*nz < 2^31, nu*nv < 2^31; positive finite spacings; SOD > 0;
+ * most 2^24) and nx*ny*nz < 2^31, nu*nv <= 2^28; positive finite spacings; SOD > 0;
  * SDD > SOD; SOD and SDD - SOD both exceed the half-diagonal of the volume grown by two
  * voxels on every side (the volume lies strictly between source and detector); finite
  * angles; no ray with z as its dominant axis.  Returns FBL_OK or FBL_E_GEOMETRY

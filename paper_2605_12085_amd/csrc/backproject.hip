@@ -65,6 +65,9 @@ constexpr int kRowCen = kWinRows / 2;      // row origin of the moment prefix (k
 constexpr int kQuantBits = 22;             // residuals are scaled to at most 2^22 in magnitude
 constexpr float kRoundMagic = 12582912.0f; // 1.5 * 2^23
 constexpr int kBufferFlags = 0x00020000;   // word 3 of a raw gfx9 buffer resource (32-bit data)
+// A buffer offset past the end of every residual window: the plan admits at most 2^28 detector
+// pixels, i.e. 2^30 bytes per view, and offsets stay far below 2^32.
+constexpr int kOutOfRange = 1 << 30;
 constexpr int kWinExtra = 16;  // columns the 16 slices' ranges may add to one slice's
 
 // Lane exchanges within a wave64.  A row is 16 consecutive lanes; DPP moves stay within a
@@ -231,9 +234,6 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
         if (bi + 1 < nb) vp_next = tab.view[vl.v[bi + 1]];
         const ColParam *__restrict__ cols = tab.col + (int64_t)view * geo.nu;
         const float *__restrict__ rwv = rw + (int64_t)(first + bi) * geo.np;
-        // the view's residual as a buffer: reads past its end return 0
-        const __amdgpu_buffer_rsrc_t rwv_rsrc =
-            __builtin_amdgcn_make_buffer_rsrc((void *)rwv, (short)0, (int)(geo.np * 4), kBufferFlags);
         // columns whose ray plane crosses the tile's xy square grown by one voxel (with a
         // column of margin): they bound the row windows below
         float umin = 3.0e38f, umax = -3.0e38f;
@@ -355,19 +355,22 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
             float wv[kColSweeps][kSegRows];
             // Loads are unconditional buffer loads, so that they issue back to back without
             // branches or address arithmetic and stay in flight until the prefix sums use
-            // them: a row or column outside the window reads a neighbouring entry of the
-            // view's residual, or 0 past its end, and build_prefix masks it before any
-            // arithmetic (so a non-finite value outside the window never reaches it).
+            // them; the buffer's bounds make every entry outside the window 0 (so a
+            // non-finite value outside it never reaches the prefix sums).
             auto load_window = [&](int h) {
-                // byte offset of this lane's first entry in the view's residual; rows step by a
-                // uniform offset (scalar registers)
-                const int vo = ((r0h[h] + wseg * kSegRows) * geo.nu + c0 + wcol) * 4;
+                // The view's residual up to the window's last row as one buffer: rows below the
+                // window read past its end, and a lane whose window column lies past the
+                // window's columns reads at kOutOfRange, so every entry outside the window
+                // loads as 0.  Rows step by a uniform offset (scalar registers).
+                const __amdgpu_buffer_rsrc_t win = __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)rwv, (short)0, (r0h[h] + nRh[h]) * geo.nu * 4, kBufferFlags);
 #pragma unroll
                 for (int cs = 0; cs < kColSweeps; ++cs) {
+                    const int col = wcol + 64 * cs;
+                    const int vo = col < nC ? ((r0h[h] + wseg * kSegRows) * geo.nu + c0 + col) * 4 : kOutOfRange;
 #pragma unroll
                     for (int j = 0; j < kSegRows; ++j)
-                        wv[cs][j] = __uint_as_float(
-                            __builtin_amdgcn_raw_buffer_load_b32(rwv_rsrc, vo + 256 * cs, j * geo.nu * 4, 0));
+                        wv[cs][j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(win, vo, j * geo.nu * 4, 0));
                 }
             };
             // Prefix sums of the loaded window: the column's scale exponent from its largest
@@ -378,11 +381,6 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
 #pragma unroll
                 for (int cs = 0; cs < kColSweeps; ++cs) {
                     const int col = wcol + 64 * cs;
-#pragma unroll
-                    for (int j = 0; j < kSegRows; ++j) {
-                        const bool keep = col < nC && wseg * kSegRows + j < nRh[h];
-                        wv[cs][j] = keep ? wv[cs][j] : 0.0f;
-                    }
                     // largest magnitude, NaN if any entry is NaN (IEEE maximum propagates it)
                     float mx = 0.0f;
 #pragma unroll

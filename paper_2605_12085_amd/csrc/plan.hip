@@ -127,7 +127,7 @@ int check_geometry(const fbl_geometry *g)
         return set_error(FBL_E_GEOMETRY, "a dimension exceeds 2^24");
     if ((double)g->nx * (double)g->ny * (double)g->nz >= 2147483648.0)
         return set_error(FBL_E_GEOMETRY, "nx*ny*nz must be below 2^31");
-    if ((double)g->nu * (double)g->nv >= 2147483648.0) return set_error(FBL_E_GEOMETRY, "nu*nv must be below 2^31");
+    if ((double)g->nu * (double)g->nv > 268435456.0) return set_error(FBL_E_GEOMETRY, "nu*nv must not exceed 2^28");
     if (g->n_views > (1 << 24)) return set_error(FBL_E_GEOMETRY, "n_views exceeds 2^24");
     if (!finite_pos(g->hx) || !finite_pos(g->hy) || !finite_pos(g->hz) || !finite_pos(g->du) || !finite_pos(g->dv))
         return set_error(FBL_E_GEOMETRY, "voxel and pixel sizes must be finite and positive");

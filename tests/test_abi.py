@@ -49,6 +49,7 @@ def test_all_configuration_geometries_are_valid():
     (dict(sod=480.0, sdd=500.0), 2, "between source and detector"),
     (dict(nv=64, dv=40.0), 2, "dominant axis is z"),
     (dict(nx=2000, ny=2000, nz=1000), 2, "2^31"),
+    (dict(nu=16385, nv=16384, du=0.003, dv=0.003), 2, "2^28"),
 ])
 def test_geometry_rejections(bad, code, needle):
     import paper_2605_12085_amd as fbl
