@@ -236,7 +236,8 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
         const float *__restrict__ rwv = rw + (int64_t)(first + bi) * geo.np;
         // columns whose ray plane crosses the tile's xy square grown by one voxel (with a
         // column of margin): they bound the row windows below
-        float umin = 3.0e38f, umax = -3.0e38f;
+        // and the depths of its corners from the source along the central ray
+        float umin = 3.0e38f, umax = -3.0e38f, dmin = 3.0e38f, dmax = -3.0e38f;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const float X = ((float)((q & 1) ? i0 + kTQ : i0 - 1) - cxv) * geo.hx;
@@ -244,10 +245,26 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
             const float u = column_of(geo, vp, X, Y);
             umin = fminf(umin, u);
             umax = fmaxf(umax, u);
+            const float dep = geo.sod - (X * vp.c + Y * vp.s);
+            dmin = fminf(dmin, dep);
+            dmax = fmaxf(dmax, dep);
         }
         const int cT0 = max(0, (int)floorf(fmaxf(umin, -4.0f)) - 1);
         const int cT1 = min(geo.nu - 1, (int)ceilf(fminf(umax, (float)geo.nu + 4.0f)) + 1);
         if (cT0 > cT1) continue;   // uniform across the block
+        {
+            // A ray's parameter at a point is the point's depth over SDD (the detector is
+            // flat and faces the source), so inside the square it lies in
+            // [dmin, dmax] / SDD, and detector row r reaches the vertical index coordinate
+            // eta there at r = cv + (eta - cz) / (tau dv/hz).  No row within two of the
+            // detector reaching eta in (k0 - 1, k0 + kTK): the view adds nothing to the tile.
+            const float e0 = (float)((double)(k0 - 1) - geo.cz), e1 = (float)((double)(k0 + kTK) - geo.cz);
+            const float s0 = geo.sdd * __builtin_amdgcn_rcpf(dmin * geo.dvz);   // 1 / (tau dv/hz)
+            const float s1 = geo.sdd * __builtin_amdgcn_rcpf(dmax * geo.dvz);
+            const float rlo = fminf(fminf(e0 * s0, e0 * s1), fminf(e1 * s0, e1 * s1)) + geo.cv;
+            const float rhi = fmaxf(fmaxf(e0 * s0, e0 * s1), fmaxf(e1 * s0, e1 * s1)) + geo.cv;
+            if (rlo > (float)(geo.nv + 1) || rhi < -2.0f) continue;   // uniform across the block
+        }
         // columns [0, split) march slices of axis_first, the rest the other axis (a view
         // whose fan crosses a diagonal has two classes, any other view one)
         for (int cls = 0; cls < 2; ++cls) {

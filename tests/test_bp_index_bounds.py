@@ -161,6 +161,39 @@ def _check_tiles(g, cols, split, WP, tiles, views, check_cover=True):
             cT1 = min(g.nu - 1, int(math.ceil(min(umax, g.nu + 4.0))) + 1)
             if cT0 > cT1:
                 continue
+            # the view is skipped when no detector row within two of the detector reaches the
+            # tile's z-range at any depth of the grown square: check that none really does
+            deps = []
+            for q in range(4):
+                X = F32((i0 + TQ if q & 1 else i0 - 1) - cxv) * F32(g.hx)
+                Y = F32((j0 + TQ if q & 2 else j0 - 1) - cyv) * F32(g.hy)
+                deps.append(float(F32(g.sod) - (X * c + Y * s)))
+            e0, e1 = F32(k0 - 1 - cz), F32(k0 + TK - cz)
+            sc = [F32(g.sdd) / (F32(d) * F32(dvz)) for d in (min(deps), max(deps))]
+            cand = [e * t for e in (e0, e1) for t in sc]
+            if min(cand) + cv > g.nv + 1 or max(cand) + cv < -2:
+                stats["skipped_z"] = stats.get("skipped_z", 0) + 1
+                for cls in range(2):
+                    ax = a0 if cls == 0 else 1 - a0
+                    lo_c = cT0 if cls == 0 else max(cT0, split[v])
+                    hi_c = min(cT1, split[v] - 1) if cls == 0 else cT1
+                    if lo_c > hi_c:
+                        continue
+                    cc = np.arange(lo_c, hi_c + 1)
+                    na_ = g.nx if ax == 0 else g.ny
+                    mt = i0 if ax == 0 else j0
+                    ms_ = np.arange(mt, min(mt + TQ, na_))
+                    qt = j0 if ax == 0 else i0
+                    # only (slice, column) pairs whose column crosses the tile
+                    xi = cols["xi0"][v, cc][None, :] + ms_[:, None] * cols["xi1"][v, cc][None, :] - qt
+                    crosses = (xi > -1.0) & (xi < TQ)
+                    tau = ms_[:, None] * cols["t1"][v, cc][None, :] + cols["t0"][v, cc][None, :]
+                    r_a = (k0 - 1 - cz) / (tau * dvz) + (g.nv - 1) / 2.0
+                    r_b = (min(k0 + TK, g.nz) - cz) / (tau * dvz) + (g.nv - 1) / 2.0
+                    first = np.maximum(np.floor(np.minimum(r_a, r_b)) + 1, 0)
+                    last = np.minimum(np.ceil(np.maximum(r_a, r_b)) - 1, g.nv - 1)
+                    assert np.all((first > last) | ~crosses), (v, i0, j0, k0)
+                continue
             for cls in range(2):
                 axis = a0 if cls == 0 else 1 - a0
                 cl0 = cT0 if cls == 0 else max(cT0, split[v])
