@@ -133,9 +133,11 @@ hipError_t launch_prescale(const fbl_plan *p, const float *r, const ViewList &vl
                            double grad_scale, float *rw, hipStream_t st);
 hipError_t launch_backproject(const fbl_plan *p, const float *rw, const ViewList &vl, int nb, int first,
                               bool accumulate, float *g, hipStream_t st);
+// The prox trial's launches (the one-pass kernel and, for many blocks, a second reduction
+// level) fill the plan's partials; the final sum is taken over final_partials[0, 3 n_final).
 hipError_t launch_step(const fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo,
-                       double hi, bool stochastic, uint64_t key, void *xbar, int64_t *n_partials_used,
-                       hipStream_t st);
+                       double hi, bool stochastic, uint64_t key, void *xbar, double **final_partials,
+                       int64_t *n_final, hipStream_t st);
 
 // FP64 check instantiation of the projector pair (y and r point at the chunk's rows).
 hipError_t launch_forward64(const fbl_plan *p, const double *x, const ViewList &vl, int nb, double *y,
@@ -152,9 +154,10 @@ hipError_t launch_mlp_adam(float *prm, const float *grad, float *m, float *v, in
 
 // Prox trial on an FP32 master iterate that also writes the 16-bit copy (plan's vol_dtype).
 hipError_t launch_step_mixed(const fbl_plan *p, const float *x, const float *g, double alpha, double mu, double lo,
-                             double hi, float *xbar, void *xbar16, int64_t *n_partials_used, hipStream_t st);
+                             double hi, float *xbar, void *xbar16, double **final_partials, int64_t *n_final,
+                             hipStream_t st);
 
-int step_blocks(const fbl_plan *p);
+int64_t step_partials_needed(int64_t d);   // FP64 partials the prox trial of d voxels writes
 int backproject_tile();   // in-slice tile extent of the backprojection (voxels)
 int backproject_tile_z(); // its extent along z (voxels)
 

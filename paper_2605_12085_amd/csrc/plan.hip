@@ -272,10 +272,11 @@ int step_call(fbl_plan *p, const void *x, const float *g, double alpha, double m
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     int64_t nparts = 0;
+    double *parts = nullptr;
     e = timed(p, FBL_K_STEP, st,
-              [&] { return launch_step(p, x, g, alpha, mu, lo, hi, stochastic, key, xbar, &nparts, st); });
+              [&] { return launch_step(p, x, g, alpha, mu, lo, hi, stochastic, key, xbar, &parts, &nparts, st); });
     if (e != hipSuccess) return hip_fail(e, "step launch");
-    e = timed(p, FBL_K_FINALIZE, st, [&] { return launch_finalize_sum(p->d_partials, nparts, 3, 1.0, red_dev, st); });
+    e = timed(p, FBL_K_FINALIZE, st, [&] { return launch_finalize_sum(parts, nparts, 3, 1.0, red_dev, st); });
     if (e != hipSuccess) return hip_fail(e, "step reduction launch");
     return ok();
 }
@@ -503,7 +504,7 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
     }
     p->fp_blocks_max = forward_blocks_per_view(G, 4);
     const int64_t np_fp = (int64_t)max_batch * p->fp_blocks_max;
-    const int64_t np_step = 3 * (int64_t)step_blocks(p);
+    const int64_t np_step = step_partials_needed((int64_t)G.nx * G.ny * G.nz);
     p->n_partials = np_fp > np_step ? np_fp : np_step;
 
     if ((rc = dev_upload(&p->d_col, col)) != FBL_OK || (rc = dev_upload(&p->d_col64, col64)) != FBL_OK ||
@@ -645,11 +646,12 @@ int fb_lisa_step_mixed(fbl_plan *p, const float *x, const float *g, double alpha
     if (rc != FBL_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     int64_t nparts = 0;
+    double *parts = nullptr;
     hipError_t e = timed(p, FBL_K_STEP, st, [&] {
-        return launch_step_mixed(p, x, g, alpha, mu, lo, hi, xbar, xbar16, &nparts, st);
+        return launch_step_mixed(p, x, g, alpha, mu, lo, hi, xbar, xbar16, &parts, &nparts, st);
     });
     if (e != hipSuccess) return hip_fail(e, "mixed step launch");
-    e = timed(p, FBL_K_FINALIZE, st, [&] { return launch_finalize_sum(p->d_partials, nparts, 3, 1.0, red_dev, st); });
+    e = timed(p, FBL_K_FINALIZE, st, [&] { return launch_finalize_sum(parts, nparts, 3, 1.0, red_dev, st); });
     if (e != hipSuccess) return hip_fail(e, "step reduction launch");
     return ok();
 }

@@ -8,7 +8,14 @@ namespace fbl {
 
 namespace {
 
-constexpr int kStepBlocks = 2048;   // 8 blocks per compute unit, grid-stride over the volume
+constexpr int kStepBlocks = 2048;   // grid-stride trial: 8 blocks per compute unit
+
+// Blocks of the grid-stride prox trial for d voxels.
+int blocks_for(int64_t d)
+{
+    const int64_t need = (d + 255) / 256;
+    return (int)(need < kStepBlocks ? need : kStepBlocks);
+}
 
 // V consecutive values of one array as a single 2-, 4-, 8- or 16-byte access.  Every
 // access is non-temporal: each voxel of x, g and xbar is touched once per launch, and
@@ -38,10 +45,12 @@ __device__ __forceinline__ void store_vec(T *__restrict__ p, int64_t q, const T 
     __builtin_nontemporal_store(t, reinterpret_cast<C *>(p) + q);
 }
 
-// Voxels per thread and pass.  With 16-bit storage four voxels share one 8-byte access
-// of x and of x-bar (and one 16-byte access of g); that measured 5-20% faster than one
-// voxel per pass at 128^3 to 1024^3.  With FP32 storage one voxel per pass streamed
-// faster at 512^3 and 1024^3 (16-byte accesses lost 9-14% there) and equally at 256^3.
+// The grid-stride prox trial: a loop over at most kStepBlocks blocks, used for volumes of
+// up to kFlatMinVoxels (below) and by the allocation-free entry point, whose FP64 partials
+// must fit a fixed scratch array.  Voxels per thread and pass: with 16-bit storage four
+// voxels share one 8-byte access of x and of x-bar (and one 16-byte access of g), 5-20%
+// faster than one voxel per pass at 128^3 to 1024^3; with FP32 storage one voxel per pass
+// (16-byte accesses lost 9-14% in this loop at 512^3 and 1024^3).
 template <typename TV> constexpr int step_vec() { return sizeof(TV) == 2 ? 4 : 1; }
 
 // SR: round the trial point stochastically (counter-based, keyed) instead of to nearest.
@@ -142,34 +151,213 @@ __global__ __launch_bounds__(256) void step_mixed_kernel(const float *__restrict
     }
 }
 
-}  // namespace
-
-hipError_t launch_step_mixed(const fbl_plan *p, const float *x, const float *g, double alpha, double mu, double lo,
-                             double hi, float *xbar, void *xbar16, int64_t *n_partials_used, hipStream_t st)
+// The three sums of a block of 256 threads, in a fixed order, written by thread 0 to
+// out[0..2]: each wave adds its lanes (a butterfly of lane exchanges), then thread 0 adds
+// the four waves' sums.  One barrier (the kernel ends after it).
+__device__ __forceinline__ void block_sums3_256(double a, double b, double c, double *__restrict__ out)
 {
-    const int blocks = step_blocks(p);
-    *n_partials_used = blocks;
-    const int64_t d = (int64_t)p->geo.nx * p->geo.ny * p->geo.nz;
-    const double amu = alpha * mu;
-    if (p->vol_dtype == FBL_BF16)
-        hipLaunchKernelGGL(step_mixed_kernel<__hip_bfloat16>, dim3(blocks), dim3(256), 0, st, x, g, alpha, amu, lo,
-                           hi, xbar, (__hip_bfloat16 *)xbar16, d, p->d_partials);
-    else if (p->vol_dtype == FBL_F16)
-        hipLaunchKernelGGL(step_mixed_kernel<__half>, dim3(blocks), dim3(256), 0, st, x, g, alpha, amu, lo, hi,
-                           xbar, (__half *)xbar16, d, p->d_partials);
-    else
-        return hipErrorInvalidValue;
+    __shared__ double red3[3][4];
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+        c += __shfl_xor(c, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red3[0][wave] = a;
+        red3[1][wave] = b;
+        red3[2][wave] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[k] = ((red3[k][0] + red3[k][1]) + red3[k][2]) + red3[k][3];
+    }
+}
+
+// The prox trial as one pass over the volume: thread t of the launch takes voxels
+// [4t, 4t + 4) (16-byte accesses of FP32 arrays, 8-byte ones of 16-bit arrays), and the
+// thread just past the last whole group takes the d mod 4 voxels left.  Every thread
+// touches one group and exits, so consecutive blocks sweep the arrays in order: at 1024^3
+// FP32 this streams at 6.5 TB/s, where a grid-stride loop over 2048 blocks (however many
+// loads it keeps in flight) reached 5.4 TB/s.  Each block writes its three FP64 sums;
+// reduce_partials_kernel and finalize_kernel add them in a fixed order.
+constexpr int kFlatV = 4;
+// Up to this many voxels the grid-stride kernels are used instead: at 256^3 their arrays
+// sit in the 256 MB last-level cache, where they ran faster (FP32 32.9 against 35.2 us,
+// BF16 27 against 35 us); from 512^3 up the one-pass kernels win (1024^3 FP32: 2.48 ->
+// 2.00 ms).
+constexpr int64_t kFlatMinVoxels = (int64_t)1 << 25;
+
+template <typename TV, bool SR>
+__global__ __launch_bounds__(256) void step_flat_kernel(const TV *__restrict__ x, const float *__restrict__ g,
+                                                        double alpha, double amu, double lo, double hi,
+                                                        uint64_t key, TV *__restrict__ xbar, int64_t d,
+                                                        double *__restrict__ partials)
+{
+#pragma clang fp contract(off)
+    constexpr int V = kFlatV;
+    double s_inner = 0.0, s_sq = 0.0, s_gg = 0.0;
+    auto trial = [&](float xf, float gf, int64_t i) -> TV {
+        const double xv = (double)xf;
+        const double gv = (double)gf;
+        double v = (xv - alpha * gv) - amu;
+        v = fmin(fmax(v, lo), hi);
+        const TV out = SR ? round_stochastic<TV>(v, key, (uint64_t)i) : from_f64<TV>(v);
+        const double dl = (double)to_f32(out) - xv;
+        s_inner += gv * dl;
+        s_sq += dl * dl;
+        s_gg += gv * gv;
+        return out;
+    };
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t dv = d / V;
+    if (q < dv) {
+        TV xv[V], out[V];
+        float gv[V];
+        load_vec<V>(x, q, xv);
+        load_vec<V>(g, q, gv);
+#pragma unroll
+        for (int k = 0; k < V; ++k) out[k] = trial(to_f32(xv[k]), gv[k], V * q + k);
+        store_vec<V>(xbar, q, out);
+    } else if (q == dv) {
+        for (int64_t i = V * dv; i < d; ++i) xbar[i] = trial(to_f32(x[i]), g[i], i);
+    }
+    block_sums3_256(s_inner, s_sq, s_gg, partials + 3 * blockIdx.x);
+}
+
+// Mixed storage in one pass: an FP32 master iterate x (read) and trial point xbar
+// (written), plus a 16-bit copy xbar16 = round-to-nearest(xbar) for the projector to read;
+// the inner products are those of the FP32 master values.  Four voxels per thread: 16-byte
+// accesses of x, g and xbar, an 8-byte access of xbar16.
+template <typename TS>
+__global__ __launch_bounds__(256) void step_mixed_flat_kernel(const float *__restrict__ x, const float *__restrict__ g,
+                                                              double alpha, double amu, double lo, double hi,
+                                                              float *__restrict__ xbar, TS *__restrict__ xbar16,
+                                                              int64_t d, double *__restrict__ partials)
+{
+#pragma clang fp contract(off)
+    constexpr int V = kFlatV;
+    double s_inner = 0.0, s_sq = 0.0, s_gg = 0.0;
+    auto trial = [&](float xf, float gf, float &out, TS &out16) {
+        const double xv = (double)xf;
+        const double gv = (double)gf;
+        double v = (xv - alpha * gv) - amu;
+        v = fmin(fmax(v, lo), hi);
+        out = (float)v;
+        out16 = from_f64<TS>((double)out);   // exact input: one rounding to nearest
+        const double dl = (double)out - xv;
+        s_inner += gv * dl;
+        s_sq += dl * dl;
+        s_gg += gv * gv;
+    };
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t dv = d / V;
+    if (q < dv) {
+        float xv[V], gv[V], out[V];
+        TS o16[V];
+        load_vec<V>(x, q, xv);
+        load_vec<V>(g, q, gv);
+#pragma unroll
+        for (int k = 0; k < V; ++k) trial(xv[k], gv[k], out[k], o16[k]);
+        store_vec<V>(xbar, q, out);
+        store_vec<V>(xbar16, q, o16);
+    } else if (q == dv) {
+        for (int64_t i = V * dv; i < d; ++i) trial(x[i], g[i], xbar[i], xbar16[i]);
+    }
+    block_sums3_256(s_inner, s_sq, s_gg, partials + 3 * blockIdx.x);
+}
+
+// Second reduction level: block r adds the three sums of blocks [1024 r, 1024 r + 1024)
+// of the first level (each thread four consecutive ones, in order, then the block's fixed
+// tree) into out[3 r + c].
+constexpr int kReduceSpan = 1024;
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double *__restrict__ in, int64_t n,
+                                                              double *__restrict__ out)
+{
+    __shared__ double red[4];
+    double s[3] = {0.0, 0.0, 0.0};
+    const int64_t i0 = (int64_t)blockIdx.x * kReduceSpan + 4 * threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (i0 + k < n) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s[c] += in[3 * (i0 + k) + c];
+        }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double t = block_sum_256(s[c], red);
+        if (threadIdx.x == 0) out[3 * blockIdx.x + c] = t;
+    }
+}
+
+// Blocks of the one-pass prox trial for d voxels, and the entries its reduction writes.
+int64_t flat_blocks(int64_t d) { return (d / kFlatV + 1 + 255) / 256; }
+int64_t reduce_blocks(int64_t first_level) { return (first_level + kReduceSpan - 1) / kReduceSpan; }
+
+// After the first level's partials[0, 3 nb): a second level when there are many, then the
+// pointer and count the final sum (finalize_kernel) takes.
+hipError_t reduce_step_partials(double *partials, int64_t nb, double **final_partials, int64_t *n_final,
+                                hipStream_t st)
+{
+    if (nb <= 2 * kReduceSpan) {
+        *final_partials = partials;
+        *n_final = nb;
+        return hipSuccess;
+    }
+    const int64_t r = reduce_blocks(nb);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)r), dim3(256), 0, st, (const double *)partials, nb,
+                       partials + 3 * nb);
+    *final_partials = partials + 3 * nb;
+    *n_final = r;
     return hipGetLastError();
 }
 
+}  // namespace
 
-static int blocks_for(int64_t d)
+int64_t step_partials_needed(int64_t d)
 {
-    const int64_t need = (d + 255) / 256;
-    return (int)(need < kStepBlocks ? need : kStepBlocks);
+    if (d <= kFlatMinVoxels) return 3 * (int64_t)kStepBlocks;
+    const int64_t nb = flat_blocks(d);
+    return 3 * (nb + reduce_blocks(nb));
 }
 
-int step_blocks(const fbl_plan *p) { return blocks_for((int64_t)p->geo.nx * p->geo.ny * p->geo.nz); }
+hipError_t launch_step_mixed(const fbl_plan *p, const float *x, const float *g, double alpha, double mu, double lo,
+                             double hi, float *xbar, void *xbar16, double **final_partials, int64_t *n_final,
+                             hipStream_t st)
+{
+    const int64_t d = (int64_t)p->geo.nx * p->geo.ny * p->geo.nz;
+    const double amu = alpha * mu;
+    if (d <= kFlatMinVoxels) {
+        const int blocks = blocks_for(d);
+        if (p->vol_dtype == FBL_BF16)
+            hipLaunchKernelGGL(step_mixed_kernel<__hip_bfloat16>, dim3(blocks), dim3(256), 0, st, x, g, alpha, amu,
+                               lo, hi, xbar, (__hip_bfloat16 *)xbar16, d, p->d_partials);
+        else if (p->vol_dtype == FBL_F16)
+            hipLaunchKernelGGL(step_mixed_kernel<__half>, dim3(blocks), dim3(256), 0, st, x, g, alpha, amu, lo, hi,
+                               xbar, (__half *)xbar16, d, p->d_partials);
+        else
+            return hipErrorInvalidValue;
+        *final_partials = p->d_partials;
+        *n_final = blocks;
+        return hipGetLastError();
+    }
+    const int64_t blocks = flat_blocks(d);
+    if (p->vol_dtype == FBL_BF16)
+        hipLaunchKernelGGL(step_mixed_flat_kernel<__hip_bfloat16>, dim3((unsigned)blocks), dim3(256), 0, st, x, g,
+                           alpha, amu, lo, hi, xbar, (__hip_bfloat16 *)xbar16, d, p->d_partials);
+    else if (p->vol_dtype == FBL_F16)
+        hipLaunchKernelGGL(step_mixed_flat_kernel<__half>, dim3((unsigned)blocks), dim3(256), 0, st, x, g, alpha,
+                           amu, lo, hi, xbar, (__half *)xbar16, d, p->d_partials);
+    else
+        return hipErrorInvalidValue;
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce_step_partials(p->d_partials, blocks, final_partials, n_final, st);
+}
+
+
+
 
 template <typename TV, bool SR>
 static hipError_t launch_step_t(int64_t d, const void *x, const float *g, double alpha, double amu, double lo,
@@ -193,18 +381,51 @@ static hipError_t launch_step_r(int32_t vol_dtype, int64_t d, const void *x, con
     }
 }
 
+template <typename TV, bool SR>
+static hipError_t launch_flat_t(int64_t d, const void *x, const float *g, double alpha, double amu, double lo,
+                                double hi, uint64_t key, void *xbar, double *partials, int64_t blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL((step_flat_kernel<TV, SR>), dim3((unsigned)blocks), dim3(256), 0, st, (const TV *)x, g, alpha,
+                       amu, lo, hi, key, (TV *)xbar, d, partials);
+    return hipGetLastError();
+}
+
+template <bool SR>
+static hipError_t launch_flat_r(int32_t vol_dtype, int64_t d, const void *x, const float *g, double alpha,
+                                double amu, double lo, double hi, uint64_t key, void *xbar, double *partials,
+                                int64_t blocks, hipStream_t st)
+{
+    switch (vol_dtype) {
+    case FBL_F32: return launch_flat_t<float, SR>(d, x, g, alpha, amu, lo, hi, key, xbar, partials, blocks, st);
+    case FBL_BF16:
+        return launch_flat_t<__hip_bfloat16, SR>(d, x, g, alpha, amu, lo, hi, key, xbar, partials, blocks, st);
+    default: return launch_flat_t<__half, SR>(d, x, g, alpha, amu, lo, hi, key, xbar, partials, blocks, st);
+    }
+}
+
 hipError_t launch_step(const fbl_plan *p, const void *x, const float *g, double alpha, double mu, double lo,
-                       double hi, bool stochastic, uint64_t key, void *xbar, int64_t *n_partials_used,
-                       hipStream_t st)
+                       double hi, bool stochastic, uint64_t key, void *xbar, double **final_partials,
+                       int64_t *n_final, hipStream_t st)
 {
     const int64_t d = (int64_t)p->geo.nx * p->geo.ny * p->geo.nz;
-    const int blocks = blocks_for(d);
-    *n_partials_used = blocks;
     const double amu = alpha * mu;
-    return stochastic
-               ? launch_step_r<true>(p->vol_dtype, d, x, g, alpha, amu, lo, hi, key, xbar, p->d_partials, blocks, st)
-               : launch_step_r<false>(p->vol_dtype, d, x, g, alpha, amu, lo, hi, key, xbar, p->d_partials, blocks,
-                                      st);
+    if (d <= kFlatMinVoxels) {
+        const int blocks = blocks_for(d);
+        *final_partials = p->d_partials;
+        *n_final = blocks;
+        return stochastic
+                   ? launch_step_r<true>(p->vol_dtype, d, x, g, alpha, amu, lo, hi, key, xbar, p->d_partials, blocks,
+                                         st)
+                   : launch_step_r<false>(p->vol_dtype, d, x, g, alpha, amu, lo, hi, key, xbar, p->d_partials, blocks,
+                                          st);
+    }
+    const int64_t blocks = flat_blocks(d);
+    const hipError_t e =
+        stochastic ? launch_flat_r<true>(p->vol_dtype, d, x, g, alpha, amu, lo, hi, key, xbar, p->d_partials, blocks, st)
+                   : launch_flat_r<false>(p->vol_dtype, d, x, g, alpha, amu, lo, hi, key, xbar, p->d_partials, blocks,
+                                          st);
+    if (e != hipSuccess) return e;
+    return reduce_step_partials(p->d_partials, blocks, final_partials, n_final, st);
 }
 
 // ---- the allocation-free prox trial ---------------------------------------------------

@@ -276,15 +276,23 @@ def test_explicit_matrix_8cubed(fbl, orc):
         assert np.abs(row - A[i]).max() <= 4e-6 * scale, i
 
 
-def test_step_parity(fbl, orc):
+# 33,752,070 voxels: above 2^25, so the prox trial takes its one-pass kernels and a
+# second reduction level; two voxels after the last group of four
+LARGE = syn.Geometry(331, 330, 309, 0.1, 0.1, 0.1, 64, 64, 0.15, 0.15, 500.0, 1000.0, 4)
+
+
+@pytest.mark.parametrize("shape", ["odd", "large"])
+def test_step_parity(fbl, orc, shape):
     import torch
-    g = ODD
+    g = ODD if shape == "odd" else LARGE
+    print("case step parity %s (%d voxels)" % (shape, g.d), flush=True)
     rng = np.random.default_rng(9)
     x = rng.uniform(0, 0.03, g.vol_shape).astype(np.float32)
     x[rng.random(g.vol_shape) < 0.2] = 0.0
     grad = rng.standard_normal(g.vol_shape).astype(np.float32) * 3.0
+    settings = ((1e-3, 0.0, 0.0, math.inf), (2.5e-3, 0.7, 0.0, 0.03), (1e-4, 2.0, 0.001, 0.025))
     with fbl.Plan(g) as plan:
-        for alpha, mu, lo, hi in ((1e-3, 0.0, 0.0, math.inf), (2.5e-3, 0.7, 0.0, 0.03), (1e-4, 2.0, 0.001, 0.025)):
+        for alpha, mu, lo, hi in (settings if shape == "odd" else settings[1:2]):
             red = torch.zeros(3, dtype=torch.float64, device="cuda")
             xb, red = fbl.fb_lisa_step(plan, _t(x), _t(grad), alpha, mu, lo, hi, red=red)
             xb = xb.cpu().numpy()

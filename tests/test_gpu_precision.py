@@ -42,6 +42,10 @@ def _dev(a64, st):
     return t.cuda()
 
 
+# 33,752,070 voxels: above 2^25, so the prox trial takes its one-pass kernels and a
+# second reduction level; two voxels after the last group of four
+LARGE = syn.Geometry(331, 330, 309, 0.1, 0.1, 0.1, 64, 64, 0.15, 0.15, 500.0, 1000.0, 4)
+
 ODD = syn.Geometry(29, 41, 37, 0.9, 1.1, 1.0, 50, 33, 1.7, 1.9, 400.0, 900.0, 12,
                    angles=[0.0, np.pi / 4, np.pi / 2, np.pi, 3 * np.pi / 2, 0.3, 1.7, 2.9, 4.0, 5.5, 0.05, 6.2])
 
@@ -87,14 +91,16 @@ def _storage_ulp(v, st):
 
 
 @pytest.mark.parametrize("st", ["bf16", "f16"])
-@pytest.mark.parametrize("shape", ["odd", "128"])
+@pytest.mark.parametrize("shape", ["odd", "128", "large"])
 def test_step_16bit_rounds_once_like_the_oracle(fbl, orc, st, shape):
     # "odd": 43,993 voxels (a tail of one after the four-voxel passes), three settings;
-    # "128": 128^3, where each thread makes several grid-stride passes of four voxels
+    # "128": 128^3, where each thread makes several grid-stride passes of four voxels;
+    # "large": above 2^25 voxels, the one-pass kernel
     import torch
-    g = ODD if shape == "odd" else syn.config_geometry("c4")
+    g = {"odd": ODD, "128": syn.config_geometry("c4"), "large": LARGE}[shape]
+    print("case step 16-bit %s %s (%d voxels)" % (st, shape, g.d), flush=True)
     settings = ((1e-3, 0.0, 0.0, math.inf), (2.5e-3, 0.7, 0.0, 0.03), (1e-4, 2.0, 0.001, 0.025))
-    if shape == "128":
+    if shape != "odd":
         settings = settings[1:2]
     rng = np.random.default_rng(22)
     xs = orc.round_storage(rng.uniform(0, 0.03, g.vol_shape), st)
@@ -203,12 +209,14 @@ def test_16bit_iterates_replay_and_error_against_fp64(fbl, orc, st, capsys):
     assert re_st <= 4 * U[st]
 
 
-@pytest.mark.parametrize("st", ["bf16", "f16", "f32"])
-def test_step_stochastic_rounding_matches_oracle(fbl, orc, st):
+@pytest.mark.parametrize("st,shape", [("bf16", "odd"), ("f16", "odd"), ("f32", "odd"), ("bf16", "large")])
+def test_step_stochastic_rounding_matches_oracle(fbl, orc, st, shape):
     # the rounding decision depends only on the FP64 trial value, the key and the voxel
     # index, so the GPU's stored trial point equals the oracle's replay of the same draw
+    # ("large": above 2^25 voxels, the one-pass kernel)
     import torch
-    g = ODD
+    g = ODD if shape == "odd" else LARGE
+    print("case step stochastic %s %s (%d voxels)" % (st, shape, g.d), flush=True)
     rng = np.random.default_rng(23)
     xs = orc.round_storage(rng.uniform(0, 0.03, g.vol_shape), st)
     xs[rng.random(g.vol_shape) < 0.2] = 0.0
@@ -257,17 +265,18 @@ def test_bf16_stochastic_iterates_replay(fbl, orc, capsys):
 
 
 @pytest.mark.parametrize("st", ["bf16", "f16"])
-@pytest.mark.parametrize("shape", ["odd", "128"])
+@pytest.mark.parametrize("shape", ["odd", "128", "large"])
 def test_step_mixed_master_and_copy(fbl, orc, st, shape):
     """Mixed storage: the FP32 trial point is the oracle's FP64 prox rounded once to FP32
     (within one FP32 ulp, > 99.9% identical), its 16-bit copy is exactly the nearest
     rounding of the returned FP32 value, and the inner products are those of the FP32
     values ("odd": a tail of one after the four-voxel passes; "128": several grid-stride
-    passes per thread)."""
+    passes per thread; "large": above 2^25 voxels, the one-pass kernel)."""
     import torch
-    g = ODD if shape == "odd" else syn.config_geometry("c4")
+    g = {"odd": ODD, "128": syn.config_geometry("c4"), "large": LARGE}[shape]
+    print("case step mixed %s %s (%d voxels)" % (st, shape, g.d), flush=True)
     settings = ((1e-3, 0.0, 0.0, math.inf), (2.5e-3, 0.7, 0.0, 0.03), (1e-4, 2.0, 0.001, 0.025))
-    if shape == "128":
+    if shape != "odd":
         settings = settings[1:2]
     rng = np.random.default_rng(24)
     x32 = rng.uniform(0, 0.03, g.vol_shape).astype(np.float32)
