@@ -482,25 +482,52 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
         rowV[(size_t)iv] = v / g->hz;
         rowV2[(size_t)iv] = (float)(v * v);
     }
-    // Backprojection launch order: a tile's work grows with the views whose fan covers
-    // it, which is all of them near the rotation axis and fewer towards the corners, so
-    // tiles are issued by increasing distance of their centre from the axis: the most
-    // work first, the least at the end of the launch, where it shortens the tail.
+    // Backprojection launch order: most work first, the least at the end of the launch,
+    // where it shortens the tail.  A tile's work grows with the views whose rays reach
+    // it: every view's fan covers the tiles near the rotation axis and fewer cover those
+    // towards the corners, and a view's cone reaches a tile high or low in the volume only
+    // where the tile lies far from its source.  The estimate counts, over up to 64 views
+    // spread over the orbit, those whose fan holds the tile's centre and whose rows reach
+    // its height there; ties go by distance from the axis.
     std::vector<int> bp_order;
     {
         const int TQ = backproject_tile(), TK = backproject_tile_z();
         const int tx = (int)((g->nx + TQ - 1) / TQ), ty = (int)((g->ny + TQ - 1) / TQ), tz = (int)((g->nz + TK - 1) / TK);
-        std::vector<double> r2((size_t)tx * ty);
+        const int64_t nxy = (int64_t)tx * ty;
+        const int nsv = (int)std::min<int64_t>(64, g->n_views);
+        const double vmax = 0.5 * (double)(g->nv - 1) * (g->dv / g->hz);   // largest row slope, index units
+        const double czz = 0.5 * (double)(g->nz - 1);
+        std::vector<double> r2((size_t)nxy);
+        std::vector<std::vector<double>> reach((size_t)nxy);   // per xy tile: |z - cz| each view reaches
         for (int j = 0; j < ty; ++j)
             for (int i = 0; i < tx; ++i) {
                 const double X = ((double)i * TQ + 0.5 * (TQ - 1) - 0.5 * (double)(g->nx - 1)) * g->hx;
                 const double Y = ((double)j * TQ + 0.5 * (TQ - 1) - 0.5 * (double)(g->ny - 1)) * g->hy;
-                r2[(size_t)j * tx + i] = X * X + Y * Y;
+                const size_t t = (size_t)j * tx + i;
+                r2[t] = X * X + Y * Y;
+                for (int k = 0; k < nsv; ++k) {
+                    const double th = p->angles_host[(int64_t)k * g->n_views / nsv];
+                    const double c = std::cos(th), sn = std::sin(th);
+                    const double dep = g->sod - (X * c + Y * sn);
+                    const double u = g->sdd * (-X * sn + Y * c) / (dep * g->du) + 0.5 * (double)(g->nu - 1);
+                    if (u < -1.0 || u > (double)g->nu) continue;   // outside the fan
+                    reach[t].push_back(dep / g->sdd * vmax);
+                }
+                std::sort(reach[t].begin(), reach[t].end());
             }
-        bp_order.resize((size_t)tx * ty * tz);
+        std::vector<int> work((size_t)nxy * tz);
+        for (int64_t t = 0; t < nxy; ++t)
+            for (int k = 0; k < tz; ++k) {
+                const double zc = std::fabs((double)k * TK + 0.5 * (TK - 1) - czz) - 0.5 * TK;
+                const auto &rv = reach[(size_t)t];
+                work[(size_t)k * nxy + t] = (int)(rv.end() - std::lower_bound(rv.begin(), rv.end(), zc));
+            }
+        bp_order.resize((size_t)nxy * tz);
         for (size_t t = 0; t < bp_order.size(); ++t) bp_order[t] = (int)t;
-        std::stable_sort(bp_order.begin(), bp_order.end(),
-                         [&](int a, int b) { return r2[(size_t)(a % (tx * ty))] < r2[(size_t)(b % (tx * ty))]; });
+        std::stable_sort(bp_order.begin(), bp_order.end(), [&](int a, int b) {
+            if (work[(size_t)a] != work[(size_t)b]) return work[(size_t)a] > work[(size_t)b];
+            return r2[(size_t)(a % nxy)] < r2[(size_t)(b % nxy)];
+        });
     }
     p->fp_blocks_max = forward_blocks_per_view(G, 4);
     const int64_t np_fp = (int64_t)max_batch * p->fp_blocks_max;
