@@ -69,6 +69,9 @@ constexpr int kBufferFlags = 0x00020000;   // word 3 of a raw gfx9 buffer resour
 // pixels, i.e. 2^30 bytes per view, and offsets stay far below 2^32.
 constexpr int kOutOfRange = 1 << 30;
 constexpr int kWinExtra = 16;  // columns the 16 slices' ranges may add to one slice's
+// Bound on the error of a detector column computed by column_of (FP32, hardware
+// reciprocal; a few 1e-4 columns at 1536 columns), with margin.
+constexpr float kColTol = 0.01f;
 
 // Lane exchanges within a wave64.  A row is 16 consecutive lanes; DPP moves stay within a
 // row, and gfx950's permlane swaps exchange whole rows.
@@ -298,11 +301,11 @@ __global__ __launch_bounds__(kThreads, WP <= 48 ? 3 : 2) void bp_kernel(const fl
                         u1 = column_of(geo, vp, ((float)(q0 + kTQ) - cxv) * geo.hx, Y);
                     }
                     // the columns strictly between u0 and u1 cross the slice within one voxel
-                    // of the tile; u is within far less than a column of its exact value, so
-                    // the floor and the ceiling of the two bound them
+                    // of the tile; u is within kColTol of its exact value, so the columns
+                    // above lo - kColTol and below hi + kColTol hold them all
                     const float lo = fminf(u0, u1), hi = fmaxf(u0, u1);
-                    a = max(cl0, (int)floorf(fmaxf(lo, -4.0f)));
-                    const int b = min(cl1, (int)ceilf(fminf(hi, (float)geo.nu + 4.0f)));
+                    a = max(cl0, (int)floorf(fmaxf(lo, -4.0f) - kColTol) + 1);
+                    const int b = min(cl1, (int)ceilf(fminf(hi, (float)geo.nu + 4.0f) + kColTol) - 1);
                     n = min(WP, max(0, b - a + 1));
                 }
                 const int incl = row_inclusive_sum(n);

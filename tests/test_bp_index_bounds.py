@@ -25,6 +25,7 @@ import synthetic as syn
 
 TQ, TK, KH = 16, 16, 8          # tile extents and z-entries per half pass (kernel constants)
 WIN_ROWS, WIN_EXTRA = 28, 16    # staged rows per column; extra window columns over the pair table
+COL_TOL = 0.01                  # the kernel's tolerance on computed detector columns
 F32 = np.float32
 
 
@@ -213,8 +214,8 @@ def _check_tiles(g, cols, split, WP, tiles, views, check_cover=True):
                     u0 = _col_of(g, c, s, np.full_like(Y, F32(q0 - 1 - cxv) * F32(g.hx)), Y)
                     u1 = _col_of(g, c, s, np.full_like(Y, F32(q0 + TQ - cxv) * F32(g.hx)), Y)
                 lo, hi = np.minimum(u0, u1), np.maximum(u0, u1)
-                a = np.maximum(cl0, np.floor(np.maximum(lo, -4.0)).astype(np.int64))
-                b = np.minimum(cl1, np.ceil(np.minimum(hi, g.nu + 4.0)).astype(np.int64))
+                a = np.maximum(cl0, np.floor(np.maximum(lo, F32(-4.0)) - F32(COL_TOL)).astype(np.int64) + 1)
+                b = np.minimum(cl1, np.ceil(np.minimum(hi, F32(g.nu + 4.0)) + F32(COL_TOL)).astype(np.int64) - 1)
                 # the table holds WP pairs per slice: a wider range would be cut silently
                 assert np.all(b - a + 1 <= WP), (v, i0, j0, k0, int((b - a + 1).max()), WP)
                 n = np.minimum(WP, np.maximum(0, b - a + 1))
