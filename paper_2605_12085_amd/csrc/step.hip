@@ -28,21 +28,29 @@ template <> struct Chunk<4> { using type = uint32_t; };
 template <> struct Chunk<8> { using type = u32x2; };
 template <> struct Chunk<16> { using type = u32x4; };
 
+// Groups of 32 bytes (eight FP32 values) are two 16-byte accesses.
 template <int V, typename T>
 __device__ __forceinline__ void load_vec(const T *__restrict__ p, int64_t q, T (&v)[V])
 {
-    using C = typename Chunk<V * sizeof(T)>::type;
-    const C t = __builtin_nontemporal_load(reinterpret_cast<const C *>(p) + q);
-    __builtin_memcpy(v, &t, sizeof(t));
+    constexpr int B = V * (int)sizeof(T);
+    constexpr int N = B > 16 ? B / 16 : 1;
+    using C = typename Chunk<B / N>::type;
+    C t[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) t[i] = __builtin_nontemporal_load(reinterpret_cast<const C *>(p) + N * q + i);
+    __builtin_memcpy(v, t, sizeof(t));
 }
 
 template <int V, typename T>
 __device__ __forceinline__ void store_vec(T *__restrict__ p, int64_t q, const T (&v)[V])
 {
-    using C = typename Chunk<V * sizeof(T)>::type;
-    C t;
-    __builtin_memcpy(&t, v, sizeof(t));
-    __builtin_nontemporal_store(t, reinterpret_cast<C *>(p) + q);
+    constexpr int B = V * (int)sizeof(T);
+    constexpr int N = B > 16 ? B / 16 : 1;
+    using C = typename Chunk<B / N>::type;
+    C t[N];
+    __builtin_memcpy(t, v, sizeof(t));
+#pragma unroll
+    for (int i = 0; i < N; ++i) __builtin_nontemporal_store(t[i], reinterpret_cast<C *>(p) + N * q + i);
 }
 
 // The grid-stride prox trial: a loop over at most kStepBlocks blocks, used for volumes of
@@ -176,13 +184,15 @@ __device__ __forceinline__ void block_sums3_256(double a, double b, double c, do
 }
 
 // The prox trial as one pass over the volume: thread t of the launch takes voxels
-// [4t, 4t + 4) (16-byte accesses of FP32 arrays, 8-byte ones of 16-bit arrays), and the
-// thread just past the last whole group takes the d mod 4 voxels left.  Every thread
-// touches one group and exits, so consecutive blocks sweep the arrays in order: at 1024^3
-// FP32 this streams at 6.5 TB/s, where a grid-stride loop over 2048 blocks (however many
-// loads it keeps in flight) reached 5.4 TB/s.  Each block writes its three FP64 sums;
-// reduce_partials_kernel and finalize_kernel add them in a fixed order.
-constexpr int kFlatV = 4;
+// [Vt, Vt + V), V = 4 with FP32 storage and 8 with 16-bit storage (16-byte accesses of x
+// and x-bar either way; g in one or two), and the thread just past the last whole group
+// takes the d mod V voxels left.  Every thread touches one group and exits, so
+// consecutive blocks sweep the arrays in order: at 1024^3 FP32 this streams at 6.5 TB/s,
+// where a grid-stride loop over 2048 blocks (however many loads it keeps in flight)
+// reached 5.4 TB/s.  Each block writes its three FP64 sums; reduce_partials_kernel and
+// finalize_kernel add them in a fixed order.
+constexpr int kFlatV = 4;   // voxels per thread of the FP32 and mixed forms
+template <typename TV> constexpr int flat_vec() { return sizeof(TV) == 2 ? 8 : kFlatV; }
 // Up to this many voxels the grid-stride kernels are used instead: at 256^3 their arrays
 // sit in the 256 MB last-level cache, where they ran faster (FP32 32.9 against 35.2 us,
 // BF16 27 against 35 us); from 512^3 up the one-pass kernels win (1024^3 FP32: 2.48 ->
@@ -196,7 +206,7 @@ __global__ __launch_bounds__(256) void step_flat_kernel(const TV *__restrict__ x
                                                         double *__restrict__ partials)
 {
 #pragma clang fp contract(off)
-    constexpr int V = kFlatV;
+    constexpr int V = flat_vec<TV>();
     double s_inner = 0.0, s_sq = 0.0, s_gg = 0.0;
     auto trial = [&](float xf, float gf, int64_t i) -> TV {
         const double xv = (double)xf;
@@ -291,8 +301,9 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double *__re
     }
 }
 
-// Blocks of the one-pass prox trial for d voxels, and the entries its reduction writes.
-int64_t flat_blocks(int64_t d) { return (d / kFlatV + 1 + 255) / 256; }
+// Blocks of the one-pass prox trial for d voxels at V voxels per thread (at most those of
+// V = kFlatV, which size the partials), and the entries its reduction writes.
+int64_t flat_blocks(int64_t d, int V = kFlatV) { return (d / V + 1 + 255) / 256; }
 int64_t reduce_blocks(int64_t first_level) { return (first_level + kReduceSpan - 1) / kReduceSpan; }
 
 // After the first level's partials[0, 3 nb): a second level when there are many, then the
@@ -381,19 +392,21 @@ static hipError_t launch_step_r(int32_t vol_dtype, int64_t d, const void *x, con
     }
 }
 
+// Launches the one-pass trial and returns its block count in *blocks.
 template <typename TV, bool SR>
 static hipError_t launch_flat_t(int64_t d, const void *x, const float *g, double alpha, double amu, double lo,
-                                double hi, uint64_t key, void *xbar, double *partials, int64_t blocks, hipStream_t st)
+                                double hi, uint64_t key, void *xbar, double *partials, int64_t *blocks, hipStream_t st)
 {
-    hipLaunchKernelGGL((step_flat_kernel<TV, SR>), dim3((unsigned)blocks), dim3(256), 0, st, (const TV *)x, g, alpha,
-                       amu, lo, hi, key, (TV *)xbar, d, partials);
+    *blocks = flat_blocks(d, flat_vec<TV>());
+    hipLaunchKernelGGL((step_flat_kernel<TV, SR>), dim3((unsigned)*blocks), dim3(256), 0, st, (const TV *)x, g,
+                       alpha, amu, lo, hi, key, (TV *)xbar, d, partials);
     return hipGetLastError();
 }
 
 template <bool SR>
 static hipError_t launch_flat_r(int32_t vol_dtype, int64_t d, const void *x, const float *g, double alpha,
                                 double amu, double lo, double hi, uint64_t key, void *xbar, double *partials,
-                                int64_t blocks, hipStream_t st)
+                                int64_t *blocks, hipStream_t st)
 {
     switch (vol_dtype) {
     case FBL_F32: return launch_flat_t<float, SR>(d, x, g, alpha, amu, lo, hi, key, xbar, partials, blocks, st);
@@ -419,11 +432,11 @@ hipError_t launch_step(const fbl_plan *p, const void *x, const float *g, double 
                    : launch_step_r<false>(p->vol_dtype, d, x, g, alpha, amu, lo, hi, key, xbar, p->d_partials, blocks,
                                           st);
     }
-    const int64_t blocks = flat_blocks(d);
+    int64_t blocks = 0;
     const hipError_t e =
-        stochastic ? launch_flat_r<true>(p->vol_dtype, d, x, g, alpha, amu, lo, hi, key, xbar, p->d_partials, blocks, st)
-                   : launch_flat_r<false>(p->vol_dtype, d, x, g, alpha, amu, lo, hi, key, xbar, p->d_partials, blocks,
-                                          st);
+        stochastic
+            ? launch_flat_r<true>(p->vol_dtype, d, x, g, alpha, amu, lo, hi, key, xbar, p->d_partials, &blocks, st)
+            : launch_flat_r<false>(p->vol_dtype, d, x, g, alpha, amu, lo, hi, key, xbar, p->d_partials, &blocks, st);
     if (e != hipSuccess) return e;
     return reduce_step_partials(p->d_partials, blocks, final_partials, n_final, st);
 }
