@@ -39,6 +39,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FP+BP GUPS & %HBM roofline; FB-LISA time-to-RMSE, learned+BF16 vs plain"
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak of the chip without packed FP32: each of 256 CUs issues one wave64 VALU
+# instruction per clock (4 SIMDs of 16 lanes, 4 clocks per instruction) at 2.4 GHz, i.e.
+# 256 * 64 * 2.4e9 lane operations per second (78.6 TFLOP/s counting an FMA as two).
+VALU_PEAK_TLOPS = 256 * 64 * 2.4e9 / 1e12
 DEVICE_DATA = ("c3", "c5")   # workloads whose exact line integrals are computed on the GPU
 
 
@@ -491,6 +495,16 @@ def projector_block(fbl, syn, name, g, cfg, b_dev, perms, steps, warmup, clock_w
         "calls": {"forward": n_fp, "backproject": n_bp, "step": sum(len(it.trials) for it in timed)},
         "mean_backtracks": float(np.mean([it.backtracks for it in timed])),
     }
+    # What binds the projector kernels is VALU issue, not HBM: both against the VALU issue
+    # peak, from the committed counter summaries (SQ_INSTS_VALU over the profiled duration).
+    alu = {}
+    for kern in (dominant, other):
+        vb = profile_value(kern, name, "valu_busy")
+        if vb is not None:
+            alu[kern] = {"bound": "alu", "achieved": round(vb * VALU_PEAK_TLOPS, 2), "peak": round(VALU_PEAK_TLOPS, 2),
+                         "unit": "T VALU lane-ops/s", "frac": vb}
+    if alu:
+        out["roofline_alu"] = alu
     if per_iteration_timing:
         out["per_launch_us"] = {k: summarize(v) for k, v in per_it.items() if v}
     return out, run
@@ -747,8 +761,8 @@ def main(argv=None):
             "parallelism": "single GPU",
         },
     }
-    for k in ("roofline", "roofline_other", "pair_frac", "kernel_us", "per_launch_us", "step_hbm", "gups_per_op",
-              "gsamples_per_s", "calls", "mean_backtracks"):
+    for k in ("roofline", "roofline_other", "roofline_alu", "pair_frac", "kernel_us", "per_launch_us", "step_hbm",
+              "gups_per_op", "gsamples_per_s", "calls", "mean_backtracks"):
         if k in blk:
             rec[k] = blk[k]
     if not args.no_cone_fraction:
@@ -806,7 +820,8 @@ def main(argv=None):
         del run2
         sec = {"workload": "c2: 256^3, 360 views, 384x384 detector, mini-batch 20, prox [0, 0.03]",
                "value": round(blk2["gups"], 3), "ms_per_step": round(blk2["wall"] / args.steps * 1e3, 3)}
-        for k in ("roofline", "roofline_other", "pair_frac", "kernel_us", "step_hbm", "calls", "mean_backtracks"):
+        for k in ("roofline", "roofline_other", "roofline_alu", "pair_frac", "kernel_us", "step_hbm", "calls",
+                  "mean_backtracks"):
             sec[k] = blk2[k]
         if model is not None:
             prop = fbl.LearnedStep(model)
