@@ -78,8 +78,12 @@ struct LineRegs {
 constexpr int fp_waves(int kb) { return kb <= 16 ? 4 : kb <= 32 ? 3 : 2; }
 
 // PARTS: parts of the slice march per ray (the block's waves are kWaves / PARTS row
-// groups of PARTS parts each).
-template <typename TV, typename TB, int KB, int PARTS>
+// groups of PARTS parts each).  RB: rays whose two line reads are issued together before
+// their lerps (1: as the compiler schedules them, which keeps one or two reads in flight
+// at this register budget).  Reading four rays' taps at once hides more LDS latency in
+// launches whose waves run in several rounds (1024^3: -2.4%, 512^3: -1.9%) but cost 1.3%
+// at 256^3, where all waves are resident at once; the results are the same to the bit.
+template <typename TV, typename TB, int KB, int PARTS, int RB = 1>
 __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
     const TV *__restrict__ x, const TV *__restrict__ xt, Geo geo, DeviceTables tab, ViewList vl, int first,
     const TB *__restrict__ b, float *__restrict__ y, double *__restrict__ partials, int blocks_per_view,
@@ -224,14 +228,33 @@ __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
                 const float A = fmaf(fl, es0, eb0);
                 const float D = fmaf(fl, ds, db);
                 float *__restrict__ base = my - P.ka * kThreads;
+                if constexpr (RB == 1) {
 #pragma unroll
-                for (int r = 0; r < kRows; ++r) {
-                    const float e = fmaf((float)r, D, A);
-                    const int j = (int)e;
-                    const float ay = __builtin_amdgcn_fractf(e);
-                    const float t0 = base[j * kThreads];
-                    const float t1 = base[(j + 1) * kThreads];
-                    part[r] += fmaf(ay, t1 - t0, t0);
+                    for (int r = 0; r < kRows; ++r) {
+                        const float e = fmaf((float)r, D, A);
+                        const int j = (int)e;
+                        const float ay = __builtin_amdgcn_fractf(e);
+                        const float t0 = base[j * kThreads];
+                        const float t1 = base[(j + 1) * kThreads];
+                        part[r] += fmaf(ay, t1 - t0, t0);
+                    }
+                } else {
+                    static_assert(kRows % RB == 0, "whole groups of rays");
+#pragma unroll
+                    for (int r0 = 0; r0 < kRows; r0 += RB) {
+                        float t0[RB], t1[RB], ay[RB];
+#pragma unroll
+                        for (int rr = 0; rr < RB; ++rr) {
+                            const float e = fmaf((float)(r0 + rr), D, A);
+                            const int j = (int)e;
+                            ay[rr] = __builtin_amdgcn_fractf(e);
+                            t0[rr] = base[j * kThreads];
+                            t1[rr] = base[(j + 1) * kThreads];
+                        }
+                        __builtin_amdgcn_sched_barrier(0);   // the group's reads are issued before its lerps
+#pragma unroll
+                        for (int rr = 0; rr < RB; ++rr) part[r0 + rr] += fmaf(ay[rr], t1[rr] - t0[rr], t0[rr]);
+                    }
                 }
             }
             P = Q;
@@ -367,22 +390,30 @@ int forward_parts(const Geo &g, int B)
 
 int forward_rows_per_thread() { return kRows; }
 
-template <typename TV, typename TB, int KB, int S>
+template <typename TV, typename TB, int KB, int S, int RB = 1>
 static hipError_t launch_fp_s(const fbl_plan *p, const void *x, const void *xt, const ViewList &vl, int nb,
                               int first, const void *b, float *y, bool want_loss, hipStream_t st)
 {
     DeviceTables tab{p->d_col, p->d_rowV, p->d_rowV2, p->d_view};
     const int bpv = forward_blocks_per_view(p->geo, S);
     dim3 grid(bpv * nb);
-    hipLaunchKernelGGL((fp_kernel<TV, TB, KB, S>), grid, dim3(kThreads), 0, st, (const TV *)x, (const TV *)xt,
+    hipLaunchKernelGGL((fp_kernel<TV, TB, KB, S, RB>), grid, dim3(kThreads), 0, st, (const TV *)x, (const TV *)xt,
                        p->geo, tab, vl, first, (const TB *)b, y, p->d_partials, bpv, want_loss ? 1 : 0);
     return hipGetLastError();
 }
+
+// Launches with at least this many waves (two rounds of four per SIMD) read four rays'
+// taps at a time (RB = 4); smaller ones keep the compiler's schedule.
+constexpr int64_t kGroupedReadWaves = 8192;
 
 template <typename TV, typename TB, int KB>
 static hipError_t launch_fp_kb(const fbl_plan *p, const void *x, const void *xt, const ViewList &vl, int nb,
                                int first, const void *b, float *y, bool want_loss, int parts, hipStream_t st)
 {
+    if constexpr (KB <= 12) {   // longer lines spill registers with four rays' taps in flight
+        if (parts == 1 && (int64_t)forward_blocks_per_view(p->geo, 1) * nb * kWaves >= kGroupedReadWaves)
+            return launch_fp_s<TV, TB, KB, 1, 4>(p, x, xt, vl, nb, first, b, y, want_loss, st);
+    }
     switch (parts) {
     case 1: return launch_fp_s<TV, TB, KB, 1>(p, x, xt, vl, nb, first, b, y, want_loss, st);
     case 2: return launch_fp_s<TV, TB, KB, 2>(p, x, xt, vl, nb, first, b, y, want_loss, st);
