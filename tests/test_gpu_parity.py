@@ -559,3 +559,29 @@ def test_full_size_sampled_parity(fbl, orc, cfg):
     gscale = np.abs(gref).max()
     assert gscale > 0
     assert np.abs(ggot - gref).max() <= TOL * gscale
+
+
+def test_grouped_forward_reads_match_the_compiler_schedule(fbl):
+    # A launch of 8192 waves or more reads four rays' line taps together before their
+    # lerps; smaller launches keep the compiler's schedule.  One call over 256 views of a
+    # 128^3 / 192^2 geometry (9 blocks of 4 waves per view: 9216 waves) takes the grouped
+    # form, the same views in two calls of 128 (4608 waves each) the other; both must give
+    # the same bits.
+    import dataclasses
+    import torch
+    g = dataclasses.replace(syn.config_geometry("c4"), n_views=256, angles=None)
+    print("case grouped forward reads 128^3, 256 views", flush=True)
+    views = np.random.default_rng(40).permutation(256).astype(np.int32)
+    x = syn.random_volume(g, seed=41)
+    b = np.random.default_rng(42).standard_normal((g.n_views, g.nv, g.nu)).astype(np.float32)
+    with fbl.Plan(g, max_batch=256) as plan:
+        xd, bd = _t(x), _t(b)
+        l_all = torch.zeros(1, dtype=torch.float64, device="cuda")
+        y_all = fbl.fb_lisa_forward(plan, xd, views, b=bd, loss=l_all, loss_scale=1.0).cpu().numpy()
+        l_two = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in range(2)]
+        y_two = np.concatenate([fbl.fb_lisa_forward(plan, xd, views[i:i + 128], b=bd, loss=l_two[i // 128],
+                                                    loss_scale=1.0).cpu().numpy() for i in (0, 128)])
+    assert np.array_equal(y_all, y_two)
+    assert np.any(y_all != 0)
+    # the loss sums the same squares in another order: equal to FP64 rounding
+    assert float(l_all) == pytest.approx(float(l_two[0]) + float(l_two[1]), rel=1e-12)
