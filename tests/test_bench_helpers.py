@@ -56,3 +56,11 @@ def test_traffic_only_for_the_source_it_was_taken_on(bench):
     rec["kernel_source_hash"] = "0" * 16
     (root / "profiles" / "bp_kernel_c2_pmc.json").write_text(json.dumps(rec))
     assert mod.measured_traffic("bp_kernel", "c2") is None          # taken on other code
+
+
+def test_valu_issue_peak(bench):
+    # 256 CUs, each issuing one wave64 VALU instruction per clock at 2.4 GHz (no packed FP32):
+    # 39.3 T lane operations per second, 78.6 TFLOP/s with an FMA counted as two
+    mod, _ = bench
+    assert mod.VALU_PEAK_TLOPS == pytest.approx(256 * 64 * 2.4e9 / 1e12)
+    assert 2 * mod.VALU_PEAK_TLOPS == pytest.approx(78.6, abs=0.05)
