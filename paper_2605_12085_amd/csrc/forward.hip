@@ -89,7 +89,10 @@ __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
     const TB *__restrict__ b, float *__restrict__ y, double *__restrict__ partials, int blocks_per_view,
     int want_loss)
 {
-    __shared__ float line[KB * kThreads];
+    // the line buffer also carries the march parts' sums to part 0
+    constexpr int kLineFloats = KB * kThreads > (PARTS - 1) * (kWaves / PARTS) * kRows * kCols
+                                    ? KB * kThreads : (PARTS - 1) * (kWaves / PARTS) * kRows * kCols;
+    __shared__ float line[kLineFloats];
     __shared__ double red[4];
     const int tiles_u = (geo.nu + kCols - 1) / kCols;
     const int lb = xcd_grouped_block((int)blockIdx.x, (int)gridDim.x);
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
     const int lane = tid & (kCols - 1), wave = tid / kCols;
     constexpr int kGroups = kWaves / PARTS;
     static_assert(kGroups * PARTS == kWaves, "PARTS divides the waves of a block");
-    static_assert((PARTS - 1) * kGroups * kRows * kCols <= KB * kThreads, "the line buffer holds the parts' sums");
+    static_assert((PARTS - 1) * kGroups * kRows * kCols <= kLineFloats, "the line buffer holds the parts' sums");
     const int grp = wave % kGroups, part = wave / kGroups;
     const int c = (tile % tiles_u) * kCols + lane;
     const int r0 = ((tile / tiles_u) * kGroups + grp) * kRows;
@@ -445,6 +448,7 @@ static hipError_t launch_fp_t(const fbl_plan *p, const void *x, const ViewList &
 {
     const void *xt = p->d_xt;
     switch (p->fp_line) {
+    case 11: return launch_fp_kb<TV, TB, 11>(p, x, xt, vl, nb, first, b, y, want_loss, parts, st);
     case 12: return launch_fp_kb<TV, TB, 12>(p, x, xt, vl, nb, first, b, y, want_loss, parts, st);
     case 16: return launch_fp_kb<TV, TB, 16>(p, x, xt, vl, nb, first, b, y, want_loss, parts, st);
     case 24: return launch_fp_kb<TV, TB, 24>(p, x, xt, vl, nb, first, b, y, want_loss, parts, st);

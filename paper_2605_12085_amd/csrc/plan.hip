@@ -375,10 +375,12 @@ int fbl_plan_create(const fbl_geometry *g, int32_t vol_dtype, int32_t proj_dtype
     // Forward: a thread's rows span at most tau_max * (rows-1) * dv/hz voxels in z on a
     // slice.  Its LDS line runs from floor(first - 1e-3) to floor(last) + 1, i.e. at most
     // floor(span + 1e-3) + 3 entries; the bound below keeps a margin for FP32 rounding.
+    // Every entry beyond the need costs two tap loads and a lerp per slice: the benchmark
+    // geometries need 11, and 12-entry lines ran 7% slower there, so 11 is compiled too.
     {
         const double span = tau_max * (double)(forward_rows_per_thread() - 1) * (g->dv / g->hz);
         const double need = std::floor(span + 0.01) + 3.0;
-        const int sizes[] = {12, 16, 24, 32, 48};
+        const int sizes[] = {11, 12, 16, 24, 32, 48};
         p->fp_line = 0;
         for (int sz : sizes)
             if (p->fp_line == 0 && need <= (double)sz) p->fp_line = sz;
