@@ -81,8 +81,9 @@ constexpr int fp_waves(int kb) { return kb <= 16 ? 4 : kb <= 32 ? 3 : 2; }
 // groups of PARTS parts each).  RB: rays whose two line reads are issued together before
 // their lerps (1: as the compiler schedules them, which keeps one or two reads in flight
 // at this register budget).  Reading four rays' taps at once hides more LDS latency in
-// launches whose waves run in several rounds (1024^3: -2.4%, 512^3: -1.9%) but cost 1.3%
-// at 256^3, where all waves are resident at once; the results are the same to the bit.
+// launches whose waves run in several rounds (1024^3: -2.4%, 512^3: -1.9%); where all
+// waves are resident at once (256^3) two at a time is best (-1.3%, four: +0.5%).  The
+// results are the same to the bit.
 template <typename TV, typename TB, int KB, int PARTS, int RB = 1>
 __global__ __launch_bounds__(kThreads, fp_waves(KB)) void fp_kernel(
     const TV *__restrict__ x, const TV *__restrict__ xt, Geo geo, DeviceTables tab, ViewList vl, int first,
@@ -406,7 +407,8 @@ static hipError_t launch_fp_s(const fbl_plan *p, const void *x, const void *xt, 
 }
 
 // Launches with at least this many waves (two rounds of four per SIMD) read four rays'
-// taps at a time (RB = 4); smaller ones keep the compiler's schedule.
+// taps at a time (RB = 4), smaller ones two (RB = 2); split marches keep the compiler's
+// schedule.
 constexpr int64_t kGroupedReadWaves = 8192;
 
 template <typename TV, typename TB, int KB>
@@ -414,8 +416,11 @@ static hipError_t launch_fp_kb(const fbl_plan *p, const void *x, const void *xt,
                                int first, const void *b, float *y, bool want_loss, int parts, hipStream_t st)
 {
     if constexpr (KB <= 12) {   // longer lines spill registers with four rays' taps in flight
-        if (parts == 1 && (int64_t)forward_blocks_per_view(p->geo, 1) * nb * kWaves >= kGroupedReadWaves)
-            return launch_fp_s<TV, TB, KB, 1, 4>(p, x, xt, vl, nb, first, b, y, want_loss, st);
+        if (parts == 1) {
+            if ((int64_t)forward_blocks_per_view(p->geo, 1) * nb * kWaves >= kGroupedReadWaves)
+                return launch_fp_s<TV, TB, KB, 1, 4>(p, x, xt, vl, nb, first, b, y, want_loss, st);
+            return launch_fp_s<TV, TB, KB, 1, 2>(p, x, xt, vl, nb, first, b, y, want_loss, st);
+        }
     }
     switch (parts) {
     case 1: return launch_fp_s<TV, TB, KB, 1>(p, x, xt, vl, nb, first, b, y, want_loss, st);

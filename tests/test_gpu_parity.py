@@ -561,12 +561,13 @@ def test_full_size_sampled_parity(fbl, orc, cfg):
     assert np.abs(ggot - gref).max() <= TOL * gscale
 
 
-def test_grouped_forward_reads_match_the_compiler_schedule(fbl):
+def test_grouped_forward_reads_agree_bit_for_bit(fbl):
     # A launch of 8192 waves or more reads four rays' line taps together before their
-    # lerps; smaller launches keep the compiler's schedule.  One call over 256 views of a
-    # 128^3 / 192^2 geometry (9 blocks of 4 waves per view: 9216 waves) takes the grouped
-    # form, the same views in two calls of 128 (4608 waves each) the other; both must give
-    # the same bits.
+    # lerps, a smaller one two.  One call over 256 views of a 128^3 / 192^2 geometry (9
+    # blocks of 4 waves per view: 9216 waves) takes the first form, the same views in two
+    # calls of 128 (4608 waves each) the second; both must give the same bits.  (The
+    # compiler-scheduled form, taken by split marches and long lines, is checked against
+    # the oracle on the small and coarse-row geometries.)
     import dataclasses
     import torch
     g = dataclasses.replace(syn.config_geometry("c4"), n_views=256, angles=None)
